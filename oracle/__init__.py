@@ -1,0 +1,132 @@
+"""CPU oracle for black-and-white connected-component labeling and analysis.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()``
+and the ``cpu_baseline`` leg of ``bench.py``.  The product path (the HIP
+library and its Python binding) never imports this package.
+
+``label(img)`` runs the plain C definition in ``ccl_oracle.c`` (pixel-level
+two-pass union-find for both polarities, direct feature sums, breadth-first
+search over the region adjacency graph for the inclusion tree, Euler number
+as #foreground components - #holes).  See that file's header for the readings
+taken where the paper (Lemaitre & Lacassagne 2020) is silent.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ccl_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+ERRORS = {-1: "invalid argument", -2: "out of memory", -3: "capacity", -4: "adjacency graph is not a tree"}
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile ``ccl_oracle.c`` into ``liboracle.so`` with plain gcc -O2."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-shared", "-fPIC", _SRC, "-o", tmp]
+        )
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _bind(lib):
+    f = lib.oracle_label
+    f.restype = ctypes.c_int64
+    f.argtypes = [
+        ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+        ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+        ctypes.c_void_p, ctypes.c_void_p,
+    ]
+    return lib
+
+
+def load_variant(path: str):
+    """Load another build of the oracle source (used by tests that plant a
+    mistake in a copy of the source and check that the pins catch it)."""
+    return _bind(ctypes.CDLL(path))
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        f = lib.oracle_label
+        f.restype = ctypes.c_int64
+        f.argtypes = [
+            ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+            ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+            ctypes.c_void_p, ctypes.c_void_p,
+        ]
+        _lib = lib
+    return _lib
+
+
+@dataclass
+class Result:
+    """Outputs of one labeling, indexed by canonical id (exterior = 0)."""
+
+    labels: np.ndarray    # int32 [h, w]
+    bbox: np.ndarray      # int64 [n, 4]: xmin, xmax, ymin, ymax
+    S: np.ndarray         # int64 [n]
+    Sx: np.ndarray        # int64 [n]
+    Sy: np.ndarray        # int64 [n]
+    parent: np.ndarray    # int32 [n]; parent[0] = -1
+    color: np.ndarray     # uint8 [n]; 1 = foreground
+    euler: int
+
+    @property
+    def n_labels(self) -> int:
+        return int(self.parent.shape[0])
+
+
+def label(img: np.ndarray, lib=None) -> Result:
+    """Label a 2-D uint8 image (nonzero = foreground); rows may be strided."""
+    img = np.asarray(img)
+    if img.dtype != np.uint8 or img.ndim != 2:
+        raise ValueError("oracle.label expects a 2-D uint8 array")
+    if img.strides[1] != 1:
+        img = np.ascontiguousarray(img)
+    h, w = img.shape
+    pitch = img.strides[0] if h > 1 else w
+    lib = lib if lib is not None else _load()
+    labels = np.empty((h, w), dtype=np.int32)
+    euler = np.zeros(1, dtype=np.int64)
+    cap = 16
+    while True:
+        feat = np.empty((cap, 7), dtype=np.int64)
+        parent = np.empty(cap, dtype=np.int32)
+        color = np.empty(cap, dtype=np.uint8)
+        n = lib.oracle_label(
+            img.ctypes.data, w, h, pitch, labels.ctypes.data, cap, feat.ctypes.data,
+            parent.ctypes.data, color.ctypes.data, euler.ctypes.data,
+        )
+        if n == -3:
+            cap = int(labels.max()) + 1 if labels.size else cap * 2
+            continue
+        if n < 0:
+            raise RuntimeError(f"oracle_label failed: {ERRORS.get(int(n), n)}")
+        break
+    n = int(n)
+    feat = feat[:n]
+    return Result(
+        labels=labels,
+        bbox=feat[:, 0:4].copy(),
+        S=feat[:, 4].copy(),
+        Sx=feat[:, 5].copy(),
+        Sy=feat[:, 6].copy(),
+        parent=parent[:n].copy(),
+        color=color[:n].copy(),
+        euler=int(euler[0]),
+    )
