@@ -1,0 +1,239 @@
+#!/usr/bin/env python3
+"""Throughput of the B&W labeling + features + tree + Euler path on one MI355X.
+
+One step = one pass of the whole path over the workload, inputs resident in
+HBM before the timed region:
+  sweep8192      25 images 8192 x 8192, Bernoulli(p) on g x g blocks,
+                 p in {.1,.3,.5,.7,.9} x g in {1,2,4,8,16} (default)
+  structured16384  one 16384 x 16384 image of nested disks + 5% salt
+Prints one JSON line (stdout); progress goes to stderr.
+
+Per-kernel durations come from HIP events recorded around every kernel of
+every call inside the timed region (ccl_label_traced, on the stream the
+kernels run on).  The roofline entry is for the dominant kernel,
+k_tile_emit, which reads every input byte and writes every output byte:
+algorithmic bytes per image = w*h*(1 + 4) + 45 * n_labels + 16.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(w: int, h: int, n_labels: int) -> int:
+    return w * h * 5 + 45 * n_labels + 16
+
+
+class HipEvents:
+    """hipEvent_t handles through the HIP runtime torch already loaded."""
+
+    def __init__(self):
+        self.rt = ctypes.CDLL("libamdhip64.so")
+        self.rt.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.rt.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+        self.rt.hipEventDestroy.argtypes = [ctypes.c_void_p]
+
+    def create(self, n):
+        arr = (ctypes.c_void_p * n)()
+        for i in range(n):
+            ev = ctypes.c_void_p()
+            rc = self.rt.hipEventCreate(ctypes.byref(ev))
+            if rc != 0:
+                raise RuntimeError(f"hipEventCreate failed ({rc})")
+            arr[i] = ev.value
+        return arr
+
+    def ms(self, a, b) -> float:
+        f = ctypes.c_float()
+        rc = self.rt.hipEventElapsedTime(ctypes.byref(f), a, b)
+        if rc != 0:
+            raise RuntimeError(f"hipEventElapsedTime failed ({rc})")
+        return float(f.value)
+
+    def destroy(self, arr):
+        for ev in arr:
+            self.rt.hipEventDestroy(ev)
+
+
+def make_workload(name: str):
+    import synth
+    if name == "sweep8192":
+        imgs = []
+        for p, g, seed, img in synth.sweep_8192():
+            imgs.append(((p, g, seed), img))
+            say(f"  generated 8192^2 p={p} g={g} seed={seed}")
+        return imgs
+    if name == "structured16384":
+        return [(("structured", 0), synth.structured(16384, 16384, seed=0))]
+    raise SystemExit(f"unknown workload {name}")
+
+
+def run_gpu(work, steps: int, warmup: int):
+    import torch
+    import paper_2006_09299_amd as ccl
+    from paper_2006_09299_amd import _capi
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    gpu_imgs = [torch.from_numpy(img).to(dev) for _, img in work]
+    torch.cuda.synchronize()
+    h, w = work[0][1].shape
+    # table capacity: true label counts from one untimed pass
+    probe = ccl.Buffers(w, h, w * h // 4 + 1024, dev)
+    counts = []
+    for t in gpu_imgs:
+        ccl.launch(t, probe)
+        torch.cuda.synchronize()
+        counts.append(int(probe.counts[0].item()))
+    del probe
+    buf = ccl.Buffers(w, h, max(counts) + 16, dev)
+    lib = _capi.lib()
+    pitch = w
+    say(f"  labels per image: min {min(counts)} max {max(counts)}")
+
+    def call(t, events=None):
+        if events is None:
+            rc = lib.ccl_label(t.data_ptr(), w, h, pitch, ctypes.byref(buf.out), buf.ws.data_ptr(), buf.ws_bytes,
+                               ctypes.c_void_p(stream.cuda_stream))
+        else:
+            rc = lib.ccl_label_traced(t.data_ptr(), w, h, pitch, ctypes.byref(buf.out), buf.ws.data_ptr(),
+                                      buf.ws_bytes, ctypes.c_void_p(stream.cuda_stream), events)
+        _capi.check(rc, "ccl_label")
+
+    for _ in range(warmup):
+        for t in gpu_imgs:
+            call(t)
+    torch.cuda.synchronize()
+
+    hip = HipEvents()
+    ev = [[hip.create(_capi.TRACE_EVENTS) for _ in gpu_imgs] for _ in range(steps)]
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record(stream)
+    for s in range(steps):
+        for i, t in enumerate(gpu_imgs):
+            call(t, ev[s][i])
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total_ms = start.elapsed_time(stop)
+
+    names = _capi.kernel_names()
+    per_kernel = {n: 0.0 for n in names}
+    emit_ms = 0.0
+    for s in range(steps):
+        for i in range(len(gpu_imgs)):
+            e = ev[s][i]
+            for k, n in enumerate(names):
+                d = hip.ms(e[k], e[k + 1])
+                per_kernel[n] += d
+                if n == "k_tile_emit":
+                    emit_ms += d
+    for row in ev:
+        for e in row:
+            hip.destroy(e)
+    launches = steps * len(gpu_imgs)
+    avg = {n: v / launches for n, v in per_kernel.items()}
+    alg = sum(algorithmic_bytes(w, h, c) for c in counts)
+    return dict(total_ms=total_ms, wall_s=wall, steps=steps, pixels_per_step=w * h * len(gpu_imgs),
+                alg_bytes_per_step=alg, kernel_avg_ms=avg, emit_avg_ms=emit_ms / launches,
+                emit_alg_bytes_per_launch=alg / len(gpu_imgs), counts=counts)
+
+
+def cpu_baseline(work, budget_s: float = 15.0):
+    """The oracle as it stands, single-threaded, on a bounded sample."""
+    import oracle
+    oracle.build(force=False)
+    order = list(range(len(work)))
+    if len(work) > 3:  # spread the sample over densities and granularities
+        order = [len(work) // 2, 0, len(work) - 1] + [i for i in range(len(work)) if i not in (0, len(work) // 2, len(work) - 1)]
+    px, secs, used = 0, 0.0, []
+    for i in order:
+        tag, img = work[i]
+        t0 = time.perf_counter()
+        oracle.label(img)
+        secs += time.perf_counter() - t0
+        px += img.size
+        used.append(tag)
+        say(f"  oracle {tag}: {secs:.1f} s so far")
+        if secs >= budget_s:
+            break
+    return dict(value=px / secs / 1e9, unit="Gpixel/s", cores=1, kind="oracle",
+                sample=f"{len(used)} of {len(work)} workload images {used}, one thread, {secs:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="sweep8192", choices=["sweep8192", "structured16384"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-also", action="store_true", help="skip the secondary structured16384 measurement")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build labels each image on a single MI355X "
+              "(multi-GPU sharding is a design note, not built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    say(f"bench: workload {args.workload}, steps {args.steps}, warmup {args.warmup}")
+    work = make_workload(args.workload)
+    r = run_gpu(work, args.steps, args.warmup)
+    ms_step = r["total_ms"] / r["steps"]
+    gpx = r["pixels_per_step"] / (ms_step / 1e3) / 1e9
+    emit_gbs = r["emit_alg_bytes_per_launch"] / (r["emit_avg_ms"] / 1e3) / 1e9
+    path_gbs = r["alg_bytes_per_step"] / (ms_step / 1e3) / 1e9
+    say(f"  {gpx:.1f} Gpixel/s, {ms_step:.3f} ms/step, kernels {json.dumps({k: round(v, 4) for k, v in r['kernel_avg_ms'].items()})}")
+    out = {
+        "metric": "Gpixel/s labeling+features+tree+Euler (1 GPU)",
+        "value": round(gpx, 3),
+        "unit": "Gpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "images_per_step": len(work),
+                   "shape": list(work[0][1].shape), "tile": list(__import__("paper_2006_09299_amd").tile_shape())},
+        "roofline": {"bound": "hbm", "kernel": "k_tile_emit", "achieved": round(emit_gbs, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(emit_gbs / HBM_PEAK_GBS, 4), "traffic": None},
+        "path_hbm": {"alg_GBs": round(path_gbs, 1), "frac": round(path_gbs / HBM_PEAK_GBS, 4)},
+        "kernel_avg_ms": {k: round(v, 5) for k, v in r["kernel_avg_ms"].items()},
+    }
+    if args.workload == "sweep8192" and not args.no_also:
+        say("bench: secondary workload structured16384")
+        w2 = make_workload("structured16384")
+        r2 = run_gpu(w2, max(2, args.steps), 1)
+        ms2 = r2["total_ms"] / r2["steps"]
+        out["also"] = {"structured16384": {
+            "Gpixel_s": round(r2["pixels_per_step"] / (ms2 / 1e3) / 1e9, 3), "ms_per_image": round(ms2, 4),
+            "path_hbm_frac": round(r2["alg_bytes_per_step"] / (ms2 / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "k_tile_emit_hbm_frac": round(r2["emit_alg_bytes_per_launch"] / (r2["emit_avg_ms"] / 1e3) / 1e9
+                                          / HBM_PEAK_GBS, 4),
+            "kernel_avg_ms": {k: round(v, 5) for k, v in r2["kernel_avg_ms"].items()}}}
+    if not args.no_cpu_baseline:
+        say("bench: cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(work)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,129 @@
+/*
+ * ccl.h -- C-ABI of the MI355X (gfx950) black-and-white connected-component
+ * labeling and analysis library (libccl.so).
+ *
+ * Operation (Lemaitre & Lacassagne, "A new run-based Connected Component
+ * Labeling for efficiently analyzing and processing holes", 2020):
+ *   - foreground (nonzero) components under 8-adjacency and background
+ *     components under 4-adjacency, found by union of runs of consecutive
+ *     rows (Sec. 3.2, B&W unification; Sec. 2, segment detection);
+ *   - the label image: every pixel receives the final label of its
+ *     component (Sec. 3.2, relabeling);
+ *   - per component the bounding box and the raw moments S, Sx, Sy
+ *     (Sec. 1; ComputeFeatures and the feature merge of the closure);
+ *   - the inclusion (adjacency) tree: the parent of a component is the unique
+ *     adjacent component that surrounds it (Sec. 3.1 definitions; obtained
+ *     from the initial adjacency of the component's first pixel);
+ *   - the Euler number, #foreground components - #holes (Sec. 1, Table 1).
+ *
+ * Conventions (readings where the paper is silent):
+ *   - the image is surrounded by a one-pixel background frame on all four
+ *     sides; the background component connected to it is the exterior, id 0;
+ *   - every other component (either colour, one id space) is numbered by the
+ *     raster rank (row-major) of its first pixel: 1, 2, ...;
+ *   - x is the column, y the row; Sx sums x, Sy sums y;
+ *   - the exterior may be empty: S = Sx = Sy = 0 and bounding box
+ *     (INT32_MAX, -1, INT32_MAX, -1).
+ * Results are exact integers and deterministic (independent of scheduling).
+ *
+ * Memory: every pointer is DEVICE memory unless marked [host].  The caller
+ * owns the input, all outputs and the workspace; the library keeps no state
+ * between calls.  All calls are asynchronous on `stream` (a hipStream_t,
+ * NULL = the null stream) and return once the work is enqueued.
+ *
+ * Errors: functions return 0 or a negative CCL_E* code; argument errors are
+ * detected on the host before anything is enqueued.  Table capacity is
+ * checked on the device: when the number of labels exceeds `cap`, the tables
+ * receive only the entries with id < cap and counts[0] still holds the true
+ * number of labels; the caller compares after synchronising.
+ */
+#ifndef CCL_H
+#define CCL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CCL_OK 0
+#define CCL_EINVAL (-1)    /* null pointer, w <= 0, h <= 0, pitch < w, w*h >= 2^31-1, cap < 1 */
+#define CCL_ENOSPC (-2)    /* workspace smaller than ccl_workspace_bytes()            */
+#define CCL_EHIP (-3)      /* the HIP runtime refused a launch                          */
+#define CCL_ECAPACITY (-4) /* (reported by callers) more labels than table capacity    */
+#define CCL_ETOOBIG (-5)   /* batch: more than 2^31-1 union-find nodes in one launch    */
+
+/* Per-component features; 40 bytes, 8-byte aligned. */
+typedef struct {
+  int32_t xmin, xmax, ymin, ymax; /* bounding box, inclusive */
+  int64_t S, Sx, Sy;              /* area, sum of x, sum of y */
+} ccl_feature_t;
+
+/* Output tables of one image.  Any table pointer may be NULL to skip it
+ * (labels == NULL gives the features-only mode: no 4 B/pixel write). */
+typedef struct {
+  int32_t *labels;          /* [h*w] row-major, row stride w: canonical id per pixel */
+  ccl_feature_t *features;  /* [cap] indexed by id */
+  int32_t *parent;          /* [cap] parent[0] = -1; parent[c] has the other colour */
+  uint8_t *color;           /* [cap] 1 = foreground, 0 = background; color[0] = 0 */
+  int64_t cap;              /* [host] table capacity (entries); w*h+1 always suffices */
+  int64_t *counts;          /* [2] out: counts[0] = number of labels, counts[1] = Euler number */
+} ccl_outputs_t;
+
+/* One image of a batch (host-side description). */
+typedef struct {
+  const uint8_t *img; /* [h*pitch] bytes, nonzero = foreground */
+  int32_t w, h;
+  int64_t pitch;      /* row stride in bytes, >= w */
+  ccl_outputs_t out;
+} ccl_image_t;
+
+/* [host] Workspace bytes needed by ccl_label for a w x h image (pure). */
+size_t ccl_workspace_bytes(int32_t w, int32_t h);
+
+/* Label one image: img[y*pitch + x], y < h, x < w.  Enqueues the whole path
+ * on `stream`.  `ws` needs no initialisation; its contents are scratch. */
+int ccl_label(const uint8_t *img, int32_t w, int32_t h, int64_t pitch, const ccl_outputs_t *out, void *ws,
+              size_t ws_bytes, void *stream);
+
+/* Number of HIP events ccl_label_traced records: one before each of the
+ * path's nine kernels, in launch order, and one after the last. */
+#define CCL_TRACE_EVENTS 10
+
+/* Same work as ccl_label, with `events` [host array of CCL_TRACE_EVENTS
+ * hipEvent_t created by the caller] recorded on `stream` around every kernel,
+ * so that per-kernel durations can be read with hipEventElapsedTime after the
+ * stream completes.  For measurement; no synchronisation is added. */
+int ccl_label_traced(const uint8_t *img, int32_t w, int32_t h, int64_t pitch, const ccl_outputs_t *out, void *ws,
+                     size_t ws_bytes, void *stream, void *const *events);
+
+/* [host] Name of kernel k (0..CCL_TRACE_EVENTS-2) in launch order, or NULL. */
+const char *ccl_kernel_name(int k);
+
+/* [host] Bytes of the descriptor block and of the workspace for a batch of
+ * `n` images described in `imgs` [host]. */
+int ccl_batch_sizes(const ccl_image_t *imgs, int32_t n, size_t *desc_bytes, size_t *ws_bytes);
+
+/* [host] Write the batch's device descriptor block into `host_desc`
+ * (desc_bytes from ccl_batch_sizes); the caller copies it to device memory
+ * (`dev_desc`) before ccl_label_batch runs. */
+int ccl_batch_prepare(const ccl_image_t *imgs, int32_t n, void *host_desc, size_t desc_bytes);
+
+/* Label `n` images in one sequence of launches (each kernel covers every
+ * tile of every image).  `dev_desc` holds the block written by
+ * ccl_batch_prepare; `imgs` [host] is the same array.  Capturable in a
+ * hipGraph: no allocation, no host synchronisation, no memset. */
+int ccl_label_batch(const ccl_image_t *imgs, int32_t n, const void *dev_desc, void *ws, size_t ws_bytes,
+                    void *stream);
+
+/* [host] Static message for a CCL_E* code. */
+const char *ccl_strerror(int code);
+
+/* [host] Tile shape compiled into this library (rows, columns). */
+void ccl_tile_shape(int32_t *tile_h, int32_t *tile_w);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CCL_H */

@@ -1,0 +1,116 @@
+"""MI355X-native black-and-white connected-component labeling and analysis.
+
+Run-based labeling after Lemaitre & Lacassagne (2020): foreground components
+(8-adjacency) and background components (4-adjacency) of a binary image,
+their bounding boxes and raw moments S, Sx, Sy, the Euler number and the
+inclusion tree, all computed by the HIP kernels of libccl.so on gfx950.
+This module only marshals arguments: PyTorch provides device memory and the
+stream; every step of the computation runs in the library's kernels.
+
+    from paper_2006_09299_amd import label
+    r = label(img)          # img: 2-D uint8 tensor on the GPU, nonzero = foreground
+    r.labels, r.bbox, r.S, r.Sx, r.Sy, r.parent, r.color, r.euler
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+from . import _capi
+from ._capi import CclError, strerror, tile_shape, workspace_bytes  # noqa: F401
+
+FEATURE_BYTES = 40  # ccl_feature_t: int32 xmin, xmax, ymin, ymax; int64 S, Sx, Sy
+
+
+@dataclass
+class Result:
+    """Outputs indexed by canonical id (exterior = 0); device tensors."""
+
+    labels: Optional[torch.Tensor]  # int32 [h, w] (None in features-only mode)
+    features: torch.Tensor          # int64 [n, 5] raw records (see bbox / S / Sx / Sy)
+    parent: torch.Tensor            # int32 [n]; parent[0] = -1
+    color: torch.Tensor             # uint8 [n]; 1 = foreground
+    n_labels: int
+    euler: int
+
+    @property
+    def bbox(self) -> torch.Tensor:  # int32 [n, 4]: xmin, xmax, ymin, ymax
+        return self.features.view(torch.int32)[:, 0:4]
+
+    @property
+    def S(self) -> torch.Tensor:
+        return self.features[:, 2]
+
+    @property
+    def Sx(self) -> torch.Tensor:
+        return self.features[:, 3]
+
+    @property
+    def Sy(self) -> torch.Tensor:
+        return self.features[:, 4]
+
+
+class Buffers:
+    """Preallocated outputs + workspace for repeated calls on one image shape."""
+
+    def __init__(self, w: int, h: int, cap: int, device, labels: bool = True):
+        self.w, self.h, self.cap = int(w), int(h), int(cap)
+        self.labels = torch.empty((h, w), dtype=torch.int32, device=device) if labels else None
+        self.features = torch.empty((cap, 5), dtype=torch.int64, device=device)
+        self.parent = torch.empty(cap, dtype=torch.int32, device=device)
+        self.color = torch.empty(cap, dtype=torch.uint8, device=device)
+        self.counts = torch.zeros(2, dtype=torch.int64, device=device)
+        self.ws_bytes = workspace_bytes(w, h)
+        self.ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=device)
+        self.out = _capi.ccl_outputs_t(
+            self.labels.data_ptr() if labels else None, self.features.data_ptr(), self.parent.data_ptr(),
+            self.color.data_ptr(), self.cap, self.counts.data_ptr())
+
+
+def _check_image(img: torch.Tensor):
+    if not isinstance(img, torch.Tensor) or img.dtype != torch.uint8 or img.dim() != 2:
+        raise ValueError("expected a 2-D uint8 tensor")
+    if not img.is_cuda:
+        raise ValueError("expected a GPU tensor (the library computes on the GPU only)")
+    if img.shape[0] < 1 or img.shape[1] < 1:
+        raise ValueError("empty image")
+    if img.stride(1) != 1:
+        raise ValueError("rows must be contiguous (stride(1) == 1)")
+    h, w = img.shape
+    pitch = img.stride(0) if h > 1 else w
+    return int(w), int(h), int(pitch)
+
+
+def launch(img: torch.Tensor, buf: Buffers, stream: Optional[int] = None) -> None:
+    """Enqueue one labeling into preallocated buffers (no synchronisation)."""
+    w, h, pitch = _check_image(img)
+    if (w, h) != (buf.w, buf.h):
+        raise ValueError("buffers were made for another shape")
+    if stream is None:
+        stream = torch.cuda.current_stream(img.device).cuda_stream
+    rc = _capi.lib().ccl_label(img.data_ptr(), w, h, pitch, ctypes.byref(buf.out), buf.ws.data_ptr(),
+                               buf.ws_bytes, ctypes.c_void_p(stream))
+    _capi.check(rc, "ccl_label")
+
+
+def label(img: torch.Tensor, cap: Optional[int] = None, labels: bool = True) -> Result:
+    """Label one image; synchronises to read the number of labels.
+
+    cap: table capacity; by default a quarter of the pixels, grown and rerun
+    when the image has more components (w*h + 1 always suffices)."""
+    w, h, pitch = _check_image(img)
+    full = w * h + 1
+    if cap is None:
+        cap = min(full, max(1024, full // 4))
+    while True:
+        buf = Buffers(w, h, cap, img.device, labels=labels)
+        launch(img, buf)
+        counts = buf.counts.cpu()
+        n, euler = int(counts[0]), int(counts[1])
+        if n <= cap:
+            break
+        cap = n
+    return Result(buf.labels, buf.features[:n], buf.parent[:n], buf.color[:n], n, euler)

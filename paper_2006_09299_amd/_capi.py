@@ -1,0 +1,109 @@
+"""ctypes view of libccl.so (include/ccl.h).  Argument marshalling only."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libccl.so")
+
+CCL_OK = 0
+CCL_EINVAL = -1
+CCL_ENOSPC = -2
+CCL_EHIP = -3
+CCL_ECAPACITY = -4
+CCL_ETOOBIG = -5
+
+
+class ccl_outputs_t(ctypes.Structure):
+    _fields_ = [
+        ("labels", ctypes.c_void_p),
+        ("features", ctypes.c_void_p),
+        ("parent", ctypes.c_void_p),
+        ("color", ctypes.c_void_p),
+        ("cap", ctypes.c_int64),
+        ("counts", ctypes.c_void_p),
+    ]
+
+
+class ccl_image_t(ctypes.Structure):
+    _fields_ = [
+        ("img", ctypes.c_void_p),
+        ("w", ctypes.c_int32),
+        ("h", ctypes.c_int32),
+        ("pitch", ctypes.c_int64),
+        ("out", ccl_outputs_t),
+    ]
+
+
+EXPORTS = (
+    "ccl_workspace_bytes", "ccl_label", "ccl_label_traced", "ccl_kernel_name", "ccl_batch_sizes",
+    "ccl_batch_prepare", "ccl_label_batch", "ccl_strerror", "ccl_tile_shape",
+)
+TRACE_EVENTS = 10
+
+_lib = None
+
+
+class CclError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {strerror(code)} ({code})")
+
+
+def lib():
+    """Load libccl.so; raises when the HIP library has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build the HIP library first (python -m paper_2006_09299_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        L.ccl_workspace_bytes.restype = ctypes.c_size_t
+        L.ccl_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
+        L.ccl_label.restype = ctypes.c_int
+        L.ccl_label.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                ctypes.POINTER(ccl_outputs_t), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+        L.ccl_label_traced.restype = ctypes.c_int
+        L.ccl_label_traced.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                       ctypes.POINTER(ccl_outputs_t), ctypes.c_void_p, ctypes.c_size_t,
+                                       ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
+        L.ccl_kernel_name.restype = ctypes.c_char_p
+        L.ccl_kernel_name.argtypes = [ctypes.c_int]
+        L.ccl_batch_sizes.restype = ctypes.c_int
+        L.ccl_batch_sizes.argtypes = [ctypes.POINTER(ccl_image_t), ctypes.c_int32,
+                                      ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
+        L.ccl_batch_prepare.restype = ctypes.c_int
+        L.ccl_batch_prepare.argtypes = [ctypes.POINTER(ccl_image_t), ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t]
+        L.ccl_label_batch.restype = ctypes.c_int
+        L.ccl_label_batch.argtypes = [ctypes.POINTER(ccl_image_t), ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_size_t, ctypes.c_void_p]
+        L.ccl_strerror.restype = ctypes.c_char_p
+        L.ccl_strerror.argtypes = [ctypes.c_int]
+        L.ccl_tile_shape.restype = None
+        L.ccl_tile_shape.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().ccl_strerror(int(code)).decode()
+
+
+def check(code: int, where: str) -> None:
+    if code != CCL_OK:
+        raise CclError(code, where)
+
+
+def workspace_bytes(w: int, h: int) -> int:
+    return int(lib().ccl_workspace_bytes(int(w), int(h)))
+
+
+def kernel_names():
+    return [lib().ccl_kernel_name(k).decode() for k in range(TRACE_EVENTS - 1)]
+
+
+def tile_shape():
+    th, tw = ctypes.c_int32(), ctypes.c_int32()
+    lib().ccl_tile_shape(ctypes.byref(th), ctypes.byref(tw))
+    return th.value, tw.value

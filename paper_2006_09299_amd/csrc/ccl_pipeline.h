@@ -1,0 +1,1246 @@
+// ccl_pipeline.h -- HIP kernels and launch sequence of the black-and-white
+// run-based connected-component labeling + analysis path for gfx950.
+//
+// Method: Lemaitre & Lacassagne, "A new run-based Connected Component
+// Labeling for efficiently analyzing and processing holes" (2020).
+//   * runs (segments) of alternating background / foreground per row
+//     (Sec. 2, segment detection);
+//   * foreground 8-adjacent, background 4-adjacent unification of runs of
+//     consecutive rows by union of equivalence classes with the minimum as
+//     representative (Sec. 3.2, B&W unification: widening by one pixel for
+//     foreground, parity fix, min-propagation / min-extraction);
+//   * features bounding box, S, Sx, Sy accumulated per run and merged into
+//     the representative (Sec. 1; ComputeFeatures and the feature merge of
+//     the transitive closure);
+//   * inclusion tree by initial adjacency: the surrounding of a component is
+//     the component of the pixel just left of its first pixel in raster order
+//     (Sec. 3.1; pointed at the final root by the closure);
+//   * Euler number = #foreground components - #holes (Sec. 1, Table 1);
+//   * relabeling of every pixel with its final label (Sec. 3.2, relabeling).
+//
+// GPU decomposition (no sequential row scan): the image is cut into TH x TW
+// tiles, one workgroup per tile.
+//   k_tile_export : pack the tile to bits, extract runs, unite runs of
+//                   consecutive rows in LDS, find which local components touch
+//                   the tile border, export them as "border nodes" with their
+//                   partial features, and count interior components per row.
+//   k_border_merge: unite border nodes across tile edges (horizontal and
+//                   vertical seams, foreground diagonals across corners) and
+//                   background on the image border with the exterior node,
+//                   atomicMin union-find in HBM.
+//   k_flatten     : final root of every border node; root takes the minimum
+//                   raster key and the sum of the partial features.
+//   k_leaders     : which border node holds its component's first pixel; rank
+//                   of that pixel among the components starting in the same
+//                   row of the same tile.
+//   k_scan_*      : exclusive scan of component starts over (row, tile column)
+//                   in raster order -> canonical id base of every such cell.
+//   k_emit_border : canonical id and features of components crossing tiles.
+//   k_tile_emit   : relabel the tile again (same code), write the label image,
+//                   features / colour / parent of every component it owns and
+//                   the Euler number contribution.
+//
+// Canonical ids: the exterior (background connected to the image border,
+// through a one-pixel background frame on all four sides) is 0; every other
+// component is numbered by the raster rank of its first pixel.
+//
+// The kernels use only HIP device features; the launch sequence is written
+// against a small launcher interface so that the same source drives the HIP
+// runtime (ccl.hip).
+#pragma once
+
+#include <stdint.h>
+
+namespace ccl {
+
+typedef unsigned long long u64;
+typedef uint32_t u32;
+typedef uint16_t u16;
+typedef uint8_t u8;
+
+// Output record, bit-identical to ccl_feature_t of include/ccl.h.
+struct Feature {
+  int32_t xmin, xmax, ymin, ymax;
+  int64_t S, Sx, Sy;
+};
+
+// One image of a launch.  All pointers are device memory.
+struct ImgDesc {
+  const u8* img;
+  int64_t pitch;
+  int32_t w, h;
+  int32_t* labels;   // [h*w] or null
+  Feature* feat;     // [cap] or null
+  int32_t* parent;   // [cap] or null
+  u8* color;         // [cap] or null
+  int64_t cap;
+  int64_t* counts;   // [2]: n_labels, Euler number
+  int32_t ntx, nty;  // tiles across / down
+  int32_t flags;     // bit0: 16-byte input loads, bit1: 16-byte label stores
+  int32_t nblk;      // scan blocks of this image
+  int64_t tile0;     // first global tile index
+  int64_t node0;     // global id of this image's exterior node
+  int64_t c0;        // offset of the (row, tile column) count grid
+  int64_t blk0;      // first scan block
+  int64_t it0;       // first border-merge work item
+  int64_t nit;       // border-merge work items
+};
+
+enum { DF_VEC_IN = 1, DF_VEC_LAB = 2 };
+
+// Workspace views (device memory), shared by all images of a launch.
+struct Work {
+  int32_t* gpar;     // [nodes] union-find parent of border nodes
+  int32_t* gkey;     // [nodes] raster index of the node's first pixel
+  int32_t* gminkey;  // [nodes] at roots: minimum key of the class
+  int32_t* grank;    // [nodes] bits 0-15 rank / interior-before, 16-21 row, 31 leader
+  int32_t* rcanon;   // [nodes] at roots: canonical id
+  Feature* gacc;     // [nodes] partial features; at roots the class sum
+  int32_t* nbt;      // [tiles] border nodes per tile
+  u16* bidx_top;     // [tiles*TW] border node index of every top-row pixel
+  u16* bidx_bot;     // [tiles*TW]
+  u16* bidx_left;    // [tiles*TH]
+  u16* bidx_right;   // [tiles*TH]
+  u64* bits_top;     // [tiles*WPR] foreground bits of the top row
+  u64* bits_bot;     // [tiles*WPR]
+  u64* bits_lr;      // [tiles*2] left column (bit = row), right column
+  int32_t* cgrid;    // [sum h*ntx] per (row, tile column): starts, then base ids
+  int32_t* bsum;     // [scan blocks]
+};
+
+constexpr u32 HI = 0x80000000u;
+constexpr int SCAN_T = 256;             // threads of the scan kernels
+constexpr int SCAN_B = SCAN_T * 4;      // entries per scan block
+
+template <int TH_, int TW_>
+struct Tile {
+  static constexpr int TH = TH_;
+  static constexpr int TW = TW_;
+  static constexpr int WPR = TW / 64;      // 64-bit words per row
+  static constexpr int NW = TH * WPR;      // words per tile
+  static constexpr int N = TH * TW;        // pixel positions per tile
+  static constexpr int CPR = TW / 16;      // 16-pixel chunks per row
+  static constexpr int NCH = TH * CPR;     // chunks per tile
+  static constexpr int BCAP = 2 * (TH + TW);  // >= border pixels >= border nodes
+  static constexpr int NT = 256;           // threads per tile workgroup
+  static constexpr int CAPI = 512;         // interior accumulators per pass
+  static_assert(TW % 64 == 0 && TW <= 1024, "tile width");
+  static_assert(TH >= 1 && TH <= 64, "tile height");
+  static_assert(N < 65536, "positions must fit 16 bits");
+  static_assert((long long)N * (TW - 1) < (1ll << 24), "packed Sx field");
+  static_assert((long long)N * (TH - 1) < (1ll << 24), "packed Sy field");
+  static_assert(NW <= 256, "prefix scan width");
+};
+
+// ---------------------------------------------------------------------------
+// small device helpers
+
+__device__ inline int clz64(u64 v) { return __builtin_clzll(v); }
+__device__ inline int ctz32(u32 v) { return __builtin_ctz(v); }
+__device__ inline int popc64(u64 v) { return __builtin_popcountll(v); }
+__device__ inline u64 low_mask(int b) { return b >= 64 ? ~0ull : ((1ull << b) - 1ull); }  // bits < b
+__device__ inline u64 valid_mask(int j, int width) {  // bits x of word j with 64*j + x < width
+  int n = width - 64 * j;
+  return n >= 64 ? ~0ull : (n <= 0 ? 0ull : ((1ull << n) - 1ull));
+}
+// nonzero bytes of a dword -> 4 bits (byte k -> bit k)
+__device__ inline u32 nz4(u32 d) {
+  u32 t = (((d & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | d) & 0x80808080u;
+  return ((t >> 7) * 0x10204080u) >> 28;
+}
+
+__device__ inline u32 ld_wg(const u32* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
+__device__ inline void st_wg(u32* p, u32 v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
+__device__ inline int ld_ag(const int32_t* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+__device__ inline void st_ag(int32_t* p, int v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+
+// Union-find in LDS over tile positions: union by minimum, path halving.
+// Path halving only ever writes an ancestor, and a successful link needs the
+// linked entry to still be a root, so concurrent finds and links are safe.
+__device__ inline u32 lfind(u32* par, u32 x) {
+  for (;;) {
+    u32 p = ld_wg(&par[x]);
+    if (p == x) return x;
+    u32 g = ld_wg(&par[p]);
+    if (g == p) return p;
+    st_wg(&par[x], g);
+    x = g;
+  }
+}
+__device__ inline void lunion(u32* par, u32 a, u32 b) {
+  for (;;) {
+    a = lfind(par, a);
+    b = lfind(par, b);
+    if (a == b) return;
+    if (a > b) { u32 t = a; a = b; b = t; }
+    u32 old = __hip_atomic_fetch_min(&par[b], a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (old == b) return;
+    b = old;  // b had been linked meanwhile: unite a with its parent
+  }
+}
+// read-only walk to the root (no writes)
+__device__ inline u32 lroot(const u32* par, u32 x) {
+  u32 p = par[x];
+  while (p != x) { x = p; p = par[x]; }
+  return x;
+}
+
+// Union-find in HBM over border nodes (same scheme, agent scope).
+__device__ inline int gfind(int32_t* gp, int x) {
+  for (;;) {
+    int p = ld_ag(&gp[x]);
+    if (p == x) return x;
+    int g = ld_ag(&gp[p]);
+    if (g == p) return p;
+    st_ag(&gp[x], g);
+    x = g;
+  }
+}
+__device__ inline void gunion(int32_t* gp, int a, int b) {
+  for (;;) {
+    a = gfind(gp, a);
+    b = gfind(gp, b);
+    if (a == b) return;
+    if (a > b) { int t = a; a = b; b = t; }
+    int old = __hip_atomic_fetch_min(&gp[b], a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old == b) return;
+    b = old;
+  }
+}
+__device__ inline int groot_ro(const int32_t* gp, int x) {
+  int p = ld_ag(&gp[x]);
+  while (p != x) { x = p; p = ld_ag(&gp[x]); }
+  return x;
+}
+
+// Pixel pairs of two consecutive rows that unite runs (B&W unification).
+// m0: lower row bits, m1: upper row bits, *p / *n: the words before / after,
+// V: valid bits of the word (pixels inside the row), pfull: the word before
+// is entirely inside the row.  Returns:
+//   vert: one bit per maximal interval of same-colour vertical pairs (both
+//         colours: 4-adjacency), unite run(lower, x) with run(upper, x);
+//   da:   foreground diagonal to the upper right, unite with run(upper, x+1)
+//         (the lower run ends at x, the upper run starts at x+1);
+//   db:   foreground diagonal to the upper left, unite with run(upper, x-1).
+struct PairMasks { u64 vert, da, db; };
+__device__ inline PairMasks pair_masks(u64 m0, u64 m1, u64 m0p, u64 m1p, u64 m0n, u64 m1n, u64 V, bool pfull) {
+  PairMasks r;
+  u64 F = m0 & m1, Fp = m0p & m1p;
+  u64 Fv = F & ~((F << 1) | (Fp >> 63));
+  u64 B = ~m0 & ~m1 & V;
+  u64 Bp = pfull ? (~m0p & ~m1p) : 0ull;
+  u64 Bv = B & ~((B << 1) | (Bp >> 63));
+  u64 R1 = (m1 >> 1) | (m1n << 63), R0 = (m0 >> 1) | (m0n << 63);
+  u64 L1 = (m1 << 1) | (m1p >> 63), L0 = (m0 << 1) | (m0p >> 63);
+  r.vert = Fv | Bv;
+  r.da = m0 & ~m1 & R1 & ~R0 & V;
+  r.db = m0 & ~m1 & L1 & ~L0 & V;
+  return r;
+}
+
+// packed per-component accumulators: S | Sx << 16 | Sy << 40 (tile-local
+// coordinates), bounding box extremes; ymin is the row of the first pixel
+struct Acc {
+  u64 s;
+  u32 xmin, xmax, ymax;
+};
+
+__device__ inline u64 seg_pack(int ly, int s, int e) {
+  u64 n = (u64)(e - s);
+  u64 sx = (u64)(s + e - 1) * n / 2;  // sum of x over [s, e)
+  u64 sy = (u64)ly * n;
+  return n | (sx << 16) | (sy << 40);
+}
+
+// ---------------------------------------------------------------------------
+// shared tile labeling (k_tile_export and k_tile_emit run the same phases)
+
+template <class T>
+struct TileSmem {
+  u64 bits[T::NW];   // foreground bits
+  u64 st[T::NW];     // run starts
+  u64 bflag[T::NW];  // roots whose component touches the tile border
+  u64 rootm[T::NW];  // roots (position p with par[p] == p at a run start)
+  u64 lmask[T::NW];  // roots that hold their component's first pixel
+  u32 par[T::N];     // union-find over positions ly * TW + x
+  u16 last[T::NW];   // x of the last run start in words <= j of the row
+  u16 bpre[T::NW];   // border roots before word (tile raster order)
+  u16 ipre[T::NW];   // interior roots before word
+  int nb, nint;
+  int euler;
+};
+
+template <class T>
+__device__ inline int run_start(const TileSmem<T>& s, int ly, int x) {
+  int j = x >> 6;
+  u64 m = s.st[ly * T::WPR + j] & (~0ull >> (63 - (x & 63)));
+  if (m) return (j << 6) + 63 - clz64(m);
+  return s.last[ly * T::WPR + j - 1];  // j > 0: bit 0 of word 0 is always a start
+}
+
+template <class T>
+__device__ inline int bidx_of(const TileSmem<T>& s, int r) {  // r: border root position
+  int wd = r >> 6;
+  return s.bpre[wd] + popc64(s.bflag[wd] & s.rootm[wd] & low_mask(r & 63));
+}
+template <class T>
+__device__ inline int iord_of(const TileSmem<T>& s, int r) {  // r: interior root position
+  int wd = r >> 6;
+  return s.ipre[wd] + popc64(~s.bflag[wd] & s.rootm[wd] & low_mask(r & 63));
+}
+
+// Phases 1-6: load + pack, runs, unite, flatten, border flags, roots, prefix.
+// Ends with a barrier; afterwards par[p] is the root position of every run
+// start p, bflag/rootm/bpre/ipre/nb/nint are valid.
+template <class T>
+__device__ void tile_label(TileSmem<T>& s, const u8* img, int64_t pitch, int x0, int y0, int tw, int th,
+                           bool vec_in) {
+  const int tid = threadIdx.x;
+  // 1. load bytes, 16 pixels per chunk -> 16 bits; par[p] = p
+  for (int c = tid; c < T::NCH; c += T::NT) {
+    int ly = c / T::CPR, cx = (c % T::CPR) * 16;
+    u32 m = 0;
+    if (ly < th && cx < tw) {
+      const u8* src = img + (int64_t)(y0 + ly) * pitch + (x0 + cx);
+      if (vec_in && cx + 16 <= tw) {
+        uint4 v = *reinterpret_cast<const uint4*>(src);
+        m = nz4(v.x) | (nz4(v.y) << 4) | (nz4(v.z) << 8) | (nz4(v.w) << 12);
+      } else {
+        int n = tw - cx < 16 ? tw - cx : 16;
+        for (int k = 0; k < n; k++) m |= (u32)(src[k] != 0) << k;
+      }
+    }
+    reinterpret_cast<u16*>(s.bits)[c] = (u16)m;
+  }
+  for (int i = tid; i < T::N; i += T::NT) s.par[i] = (u32)i;
+  for (int i = tid; i < T::NW; i += T::NT) s.bflag[i] = 0;
+  __syncthreads();
+
+  // 2. run starts per row; last start per word
+  for (int ly = tid; ly < T::TH; ly += T::NT) {
+    int lastx = 0;
+    for (int j = 0; j < T::WPR; j++) {
+      u64 b = s.bits[ly * T::WPR + j];
+      u64 carry = j ? (s.bits[ly * T::WPR + j - 1] >> 63) : (~b & 1ull);
+      u64 e = (b ^ ((b << 1) | carry)) & valid_mask(j, tw);
+      if (ly >= th) e = 0;
+      s.st[ly * T::WPR + j] = e;
+      if (e) lastx = j * 64 + 63 - clz64(e);
+      s.last[ly * T::WPR + j] = (u16)lastx;
+    }
+  }
+  __syncthreads();
+
+  // 3. unite runs of rows ly-1, ly
+  for (int c = tid; c < T::NCH; c += T::NT) {
+    int ly = c / T::CPR, cc = c % T::CPR;
+    if (ly == 0 || ly >= th || cc * 16 >= tw) continue;
+    int j = cc >> 2, sh = (cc & 3) * 16;
+    const u64* B0 = &s.bits[ly * T::WPR];
+    const u64* B1 = &s.bits[(ly - 1) * T::WPR];
+    u64 m0 = B0[j], m1 = B1[j];
+    u64 m0p = j ? B0[j - 1] : 0ull, m1p = j ? B1[j - 1] : 0ull;
+    u64 m0n = j + 1 < T::WPR ? B0[j + 1] : 0ull, m1n = j + 1 < T::WPR ? B1[j + 1] : 0ull;
+    PairMasks pm = pair_masks(m0, m1, m0p, m1p, m0n, m1n, valid_mask(j, tw), j > 0);
+    u32 vv = (u32)(pm.vert >> sh) & 0xFFFFu;
+    u32 da = (u32)(pm.da >> sh) & 0xFFFFu;
+    u32 db = (u32)(pm.db >> sh) & 0xFFFFu;
+    const u32 r0 = (u32)(ly * T::TW), r1 = (u32)((ly - 1) * T::TW);
+    const int xb = j * 64 + sh;
+    while (vv) {
+      int x = xb + ctz32(vv);
+      vv &= vv - 1;
+      lunion(s.par, r0 + run_start(s, ly, x), r1 + run_start(s, ly - 1, x));
+    }
+    while (da) {
+      int x = xb + ctz32(da);
+      da &= da - 1;
+      lunion(s.par, r0 + run_start(s, ly, x), r1 + run_start(s, ly - 1, x + 1));
+    }
+    while (db) {
+      int x = xb + ctz32(db);
+      db &= db - 1;
+      lunion(s.par, r0 + run_start(s, ly, x), r1 + run_start(s, ly - 1, x - 1));
+    }
+  }
+  __syncthreads();
+
+  // 4. flatten: every run start points at its root (own entry written only)
+  for (int c = tid; c < T::NCH; c += T::NT) {
+    int ly = c / T::CPR, cc = c % T::CPR;
+    if (ly >= th) continue;
+    int j = cc >> 2, sh = (cc & 3) * 16;
+    u32 m = (u32)(s.st[ly * T::WPR + j] >> sh) & 0xFFFFu;
+    while (m) {
+      u32 p = (u32)(ly * T::TW + j * 64 + sh + ctz32(m));
+      m &= m - 1;
+      s.par[p] = lroot(s.par, p);
+    }
+  }
+  __syncthreads();
+
+  // 5. roots of components touching the tile border
+  for (int t = tid; t < 2 * T::CPR + 2 * T::TH; t += T::NT) {
+    if (t < 2 * T::CPR) {  // top / bottom row, one chunk each
+      int ly = t < T::CPR ? 0 : th - 1;
+      int cc = t % T::CPR;
+      int j = cc >> 2, sh = (cc & 3) * 16;
+      u32 m = (u32)(s.st[ly * T::WPR + j] >> sh) & 0xFFFFu;
+      while (m) {
+        u32 p = (u32)(ly * T::TW + j * 64 + sh + ctz32(m));
+        m &= m - 1;
+        u32 r = s.par[p];
+        atomicOr(&s.bflag[r >> 6], 1ull << (r & 63));
+      }
+    } else {
+      int k = t - 2 * T::CPR;
+      int ly = k % T::TH;
+      if (ly >= th) continue;
+      int x = k < T::TH ? 0 : run_start(s, ly, tw - 1);
+      u32 r = s.par[ly * T::TW + x];
+      atomicOr(&s.bflag[r >> 6], 1ull << (r & 63));
+    }
+  }
+  __syncthreads();
+
+  // 6. root masks
+  for (int c = tid; c < T::NCH; c += T::NT) {
+    int ly = c / T::CPR, cc = c % T::CPR;
+    int j = cc >> 2, sh = (cc & 3) * 16;
+    u32 m = ly < th ? (u32)(s.st[ly * T::WPR + j] >> sh) & 0xFFFFu : 0u;
+    u32 rm = 0;
+    while (m) {
+      int k = ctz32(m);
+      m &= m - 1;
+      u32 p = (u32)(ly * T::TW + j * 64 + sh + k);
+      if (s.par[p] == p) rm |= 1u << k;
+    }
+    reinterpret_cast<u16*>(s.rootm)[c] = (u16)rm;
+  }
+  __syncthreads();
+
+  // 7. exclusive prefix counts of border / interior roots over words
+  if (tid < 64) {
+    u32 cb = 0, ci = 0;
+    for (int base = 0; base < T::NW; base += 64) {
+      int wd = base + tid;
+      u64 rm = wd < T::NW ? s.rootm[wd] : 0ull;
+      u64 bf = wd < T::NW ? s.bflag[wd] : 0ull;
+      u32 nb = (u32)popc64(rm & bf), ni = (u32)popc64(rm & ~bf);
+      u32 v = nb | (ni << 16);  // both counts <= 4096 per 64 words
+      u32 inc = v;
+      for (int d = 1; d < 64; d <<= 1) {
+        u32 t = __shfl_up(inc, d, 64);
+        if (tid >= d) inc += t;
+      }
+      u32 exc = inc - v;
+      if (wd < T::NW) {
+        s.bpre[wd] = (u16)(cb + (exc & 0xFFFFu));
+        s.ipre[wd] = (u16)(ci + (exc >> 16));
+      }
+      u32 tot = __shfl(inc, 63, 64);
+      cb += tot & 0xFFFFu;
+      ci += tot >> 16;
+    }
+    if (tid == 0) {
+      s.nb = (int)cb;
+      s.nint = (int)ci;
+    }
+  }
+  __syncthreads();
+}
+
+// Segments of one 16-pixel chunk: calls f(run_start_x, seg_begin, seg_end).
+template <class T, class Fn>
+__device__ inline void for_segments(const TileSmem<T>& s, int ly, int cc, int tw, Fn f) {
+  int cs = cc * 16;
+  if (cs >= tw) return;
+  int ce = cs + 16 < tw ? cs + 16 : tw;
+  int j = cc >> 2, sh = (cc & 3) * 16;
+  u32 m = ((u32)(s.st[ly * T::WPR + j] >> sh) & 0xFFFFu) & ~1u;
+  int start = run_start(s, ly, cs);
+  int x = cs;
+  for (;;) {
+    int nx = m ? cs + ctz32(m) : ce;
+    f(start, x, nx);
+    if (!m) break;
+    m &= m - 1;
+    start = nx;
+    x = nx;
+  }
+}
+
+__device__ inline void acc_init(Acc& a) {
+  a.s = 0;
+  a.xmin = 0xFFFFu;
+  a.xmax = 0;
+  a.ymax = 0;
+}
+__device__ inline void acc_add(Acc& a, int ly, int s0, int e0) {
+  atomicAdd(&a.s, seg_pack(ly, s0, e0));
+  atomicMin(&a.xmin, (u32)s0);
+  atomicMax(&a.xmax, (u32)(e0 - 1));
+  atomicMax(&a.ymax, (u32)ly);
+}
+__device__ inline Feature acc_abs(const Acc& a, int ly_min, int x0, int y0) {
+  Feature f;
+  int64_t S = (int64_t)(a.s & 0xFFFFull);
+  int64_t sx = (int64_t)((a.s >> 16) & 0xFFFFFFull);
+  int64_t sy = (int64_t)(a.s >> 40);
+  f.xmin = (int32_t)a.xmin + x0;
+  f.xmax = (int32_t)a.xmax + x0;
+  f.ymin = ly_min + y0;
+  f.ymax = (int32_t)a.ymax + y0;
+  f.S = S;
+  f.Sx = sx + S * x0;
+  f.Sy = sy + S * y0;
+  return f;
+}
+
+// ---------------------------------------------------------------------------
+// descriptor sources: one image by value, or an array in device memory
+
+struct OneImage {
+  ImgDesc d;
+  __device__ const ImgDesc& by_tile(int64_t) const { return d; }
+  __device__ const ImgDesc& by_item(int64_t) const { return d; }
+  __device__ const ImgDesc& by_block(int64_t) const { return d; }
+  __device__ const ImgDesc& by_index(int64_t) const { return d; }
+  __device__ int64_t count() const { return 1; }
+};
+
+struct ManyImages {
+  const ImgDesc* ds;
+  int32_t n;
+  // last descriptor whose field `first` is <= v (descriptors sorted by it)
+  template <class Get>
+  __device__ const ImgDesc& search(int64_t v, Get get) const {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+      int mid = (lo + hi + 1) >> 1;
+      if (get(ds[mid]) <= v) lo = mid;
+      else hi = mid - 1;
+    }
+    return ds[lo];
+  }
+  __device__ const ImgDesc& by_tile(int64_t t) const { return search(t, [](const ImgDesc& d) { return d.tile0; }); }
+  __device__ const ImgDesc& by_item(int64_t i) const { return search(i, [](const ImgDesc& d) { return d.it0; }); }
+  __device__ const ImgDesc& by_block(int64_t b) const { return search(b, [](const ImgDesc& d) { return d.blk0; }); }
+  __device__ const ImgDesc& by_index(int64_t i) const { return ds[i]; }
+  __device__ int64_t count() const { return n; }
+};
+
+template <class T>
+__device__ inline int64_t tile_node_base(const ImgDesc& d, int64_t lt) {  // slot 0 of local tile lt
+  return d.node0 + 1 + lt * T::BCAP;
+}
+
+// ---------------------------------------------------------------------------
+// K1: tile labeling and export of border nodes
+
+template <class T, class Src>
+__global__ void __launch_bounds__(256) k_tile_export(Src src, Work wk) {
+  __shared__ TileSmem<T> s;
+  __shared__ Acc bacc[T::BCAP];
+  const int64_t gt = blockIdx.x;
+  const ImgDesc& d = src.by_tile(gt);
+  const int64_t lt = gt - d.tile0;
+  const int tx = (int)(lt % d.ntx), ty = (int)(lt / d.ntx);
+  const int x0 = tx * T::TW, y0 = ty * T::TH;
+  const int tw = d.w - x0 < T::TW ? d.w - x0 : T::TW;
+  const int th = d.h - y0 < T::TH ? d.h - y0 : T::TH;
+  const int tid = threadIdx.x;
+
+  if (lt == 0 && tid == 0) {  // per-image state read by later kernels
+    wk.gpar[d.node0] = (int32_t)d.node0;
+    wk.gminkey[d.node0] = -1;
+    wk.gkey[d.node0] = -1;
+    Feature e;
+    e.xmin = 0x7FFFFFFF; e.xmax = -1; e.ymin = 0x7FFFFFFF; e.ymax = -1;
+    e.S = 0; e.Sx = 0; e.Sy = 0;
+    wk.gacc[d.node0] = e;
+    if (d.counts) d.counts[1] = 0;
+  }
+
+  tile_label<T>(s, d.img, d.pitch, x0, y0, tw, th, (d.flags & DF_VEC_IN) != 0);
+
+  const int64_t nbase = tile_node_base<T>(d, lt);
+  // 8. border node records, interior counts per row, accumulator init
+  for (int wd = tid; wd < T::NW; wd += T::NT) {
+    int ly = wd / T::WPR, j = wd % T::WPR;
+    u64 bm = s.rootm[wd] & s.bflag[wd];
+    u64 im = s.rootm[wd] & ~s.bflag[wd];
+    int ib_row = s.ipre[wd] - s.ipre[ly * T::WPR];
+    while (bm) {
+      int k = __builtin_ctzll(bm);
+      bm &= bm - 1;
+      int x = j * 64 + k;
+      int bi = s.bpre[wd] + popc64(s.rootm[wd] & s.bflag[wd] & low_mask(k));
+      int64_t node = nbase + bi;
+      int32_t key = (int32_t)((int64_t)(y0 + ly) * d.w + x0 + x);
+      wk.gpar[node] = (int32_t)node;
+      wk.gkey[node] = key;
+      wk.gminkey[node] = key;
+      wk.grank[node] = (ib_row + popc64(im & low_mask(k))) | (ly << 16);
+      acc_init(bacc[bi]);
+    }
+  }
+  for (int ly = tid; ly < th; ly += T::NT) {
+    int cnt = 0;
+    for (int j = 0; j < T::WPR; j++) cnt += popc64(s.rootm[ly * T::WPR + j] & ~s.bflag[ly * T::WPR + j]);
+    wk.cgrid[d.c0 + (int64_t)(y0 + ly) * d.ntx + tx] = cnt;
+  }
+  if (tid == 0) wk.nbt[gt] = s.nb;
+  __syncthreads();
+
+  // 9. partial features of border components
+  for (int c = tid; c < T::NCH; c += T::NT) {
+    int ly = c / T::CPR, cc = c % T::CPR;
+    if (ly >= th) continue;
+    for_segments<T>(s, ly, cc, tw, [&](int start, int a, int b) {
+      u32 r = s.par[ly * T::TW + start];
+      if (s.bflag[r >> 6] & (1ull << (r & 63))) acc_add(bacc[bidx_of<T>(s, (int)r)], ly, a, b);
+    });
+  }
+  __syncthreads();
+
+  // 10. write partial features and the border arrays
+  for (int wd = tid; wd < T::NW; wd += T::NT) {
+    int ly = wd / T::WPR, j = wd % T::WPR;
+    u64 bm = s.rootm[wd] & s.bflag[wd];
+    while (bm) {
+      int k = __builtin_ctzll(bm);
+      bm &= bm - 1;
+      int bi = s.bpre[wd] + popc64(s.rootm[wd] & s.bflag[wd] & low_mask(k));
+      (void)j;
+      wk.gacc[nbase + bi] = acc_abs(bacc[bi], ly, x0, y0);
+    }
+  }
+  for (int t = tid; t < 2 * T::TW + 2 * T::TH; t += T::NT) {
+    if (t < 2 * T::TW) {
+      int bottom = t >= T::TW;
+      int x = t % T::TW;
+      int ly = bottom ? th - 1 : 0;
+      u16 v = 0xFFFFu;
+      if (x < tw) v = (u16)bidx_of<T>(s, (int)s.par[ly * T::TW + run_start(s, ly, x)]);
+      (bottom ? wk.bidx_bot : wk.bidx_top)[gt * T::TW + x] = v;
+    } else {
+      int k = t - 2 * T::TW;
+      int right = k >= T::TH;
+      int ly = k % T::TH;
+      u16 v = 0xFFFFu;
+      if (ly < th) {
+        int x = right ? run_start(s, ly, tw - 1) : 0;
+        v = (u16)bidx_of<T>(s, (int)s.par[ly * T::TW + x]);
+      }
+      (right ? wk.bidx_right : wk.bidx_left)[gt * T::TH + ly] = v;
+    }
+  }
+  for (int t = tid; t < 2 * T::WPR + 2; t += T::NT) {
+    if (t < T::WPR) wk.bits_top[gt * T::WPR + t] = s.bits[t];
+    else if (t < 2 * T::WPR) wk.bits_bot[gt * T::WPR + (t - T::WPR)] = s.bits[(th - 1) * T::WPR + (t - T::WPR)];
+    else {
+      int right = t - 2 * T::WPR;
+      u64 col = 0;
+      int x = right ? tw - 1 : 0;
+      for (int ly = 0; ly < th; ly++) col |= ((s.bits[ly * T::WPR + (x >> 6)] >> (x & 63)) & 1ull) << ly;
+      wk.bits_lr[gt * 2 + right] = col;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K2: unions across tile seams and with the exterior
+
+template <class T>
+__device__ inline u64 seam_bits(const Work& wk, const ImgDesc& d, int tile_row, int jw, bool bottom) {
+  int nwr = (d.w + 63) >> 6;
+  if (jw < 0 || jw >= nwr) return 0ull;
+  int tcol = jw / T::WPR, j = jw % T::WPR;
+  int64_t gt = d.tile0 + (int64_t)tile_row * d.ntx + tcol;
+  return (bottom ? wk.bits_bot : wk.bits_top)[gt * T::WPR + j];
+}
+template <class T>
+__device__ inline int seam_node(const Work& wk, const ImgDesc& d, int tile_row, int x, bool bottom) {
+  int tcol = x / T::TW;
+  int64_t lt = (int64_t)tile_row * d.ntx + tcol;
+  int64_t gt = d.tile0 + lt;
+  u16 b = (bottom ? wk.bidx_bot : wk.bidx_top)[gt * T::TW + (x % T::TW)];
+  return (int)(tile_node_base<T>(d, lt) + b);
+}
+template <class T>
+__device__ inline int col_node(const Work& wk, const ImgDesc& d, int tcol, int y, bool right) {
+  int64_t lt = (int64_t)(y / T::TH) * d.ntx + tcol;
+  int64_t gt = d.tile0 + lt;
+  u16 b = (right ? wk.bidx_right : wk.bidx_left)[gt * T::TH + (y % T::TH)];
+  return (int)(tile_node_base<T>(d, lt) + b);
+}
+template <class T>
+__device__ inline int col_bit(const Work& wk, const ImgDesc& d, int tcol, int y, bool right) {
+  int64_t gt = d.tile0 + (int64_t)(y / T::TH) * d.ntx + tcol;
+  return (int)((wk.bits_lr[gt * 2 + (right ? 1 : 0)] >> (y % T::TH)) & 1ull);
+}
+
+template <class T>
+__host__ __device__ inline int64_t merge_items(int w, int h, int ntx, int nty) {
+  int64_t nwr = (w + 63) / 64;
+  return (int64_t)(nty - 1) * nwr + (int64_t)(ntx - 1) * h + 2 * nwr + 2 * (int64_t)h;
+}
+
+template <class T, class Src>
+__global__ void __launch_bounds__(256) k_border_merge(Src src, Work wk, int64_t total) {
+  const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gi >= total) return;
+  const ImgDesc& d = src.by_item(gi);
+  int64_t i = gi - d.it0;
+  const int nwr = (d.w + 63) >> 6;
+  const int ext = (int)d.node0;
+  const int64_t nH = (int64_t)(d.nty - 1) * nwr;
+  const int64_t nV = (int64_t)(d.ntx - 1) * d.h;
+  if (i < nH) {  // horizontal seam: bottom row of tile row e-1 above top row of tile row e
+    int e = (int)(i / nwr) + 1, jw = (int)(i % nwr);
+    u64 m0 = seam_bits<T>(wk, d, e, jw, false), m1 = seam_bits<T>(wk, d, e - 1, jw, true);
+    u64 m0p = seam_bits<T>(wk, d, e, jw - 1, false), m1p = seam_bits<T>(wk, d, e - 1, jw - 1, true);
+    u64 m0n = seam_bits<T>(wk, d, e, jw + 1, false), m1n = seam_bits<T>(wk, d, e - 1, jw + 1, true);
+    PairMasks pm = pair_masks(m0, m1, m0p, m1p, m0n, m1n, valid_mask(jw, d.w), jw > 0);
+    int xb = jw * 64;
+    u64 m = pm.vert;
+    while (m) {
+      int x = xb + __builtin_ctzll(m);
+      m &= m - 1;
+      gunion(wk.gpar, seam_node<T>(wk, d, e, x, false), seam_node<T>(wk, d, e - 1, x, true));
+    }
+    m = pm.da;
+    while (m) {
+      int x = xb + __builtin_ctzll(m);
+      m &= m - 1;
+      gunion(wk.gpar, seam_node<T>(wk, d, e, x, false), seam_node<T>(wk, d, e - 1, x + 1, true));
+    }
+    m = pm.db;
+    while (m) {
+      int x = xb + __builtin_ctzll(m);
+      m &= m - 1;
+      gunion(wk.gpar, seam_node<T>(wk, d, e, x, false), seam_node<T>(wk, d, e - 1, x - 1, true));
+    }
+    return;
+  }
+  i -= nH;
+  if (i < nV) {  // vertical seam between tile columns e-1 and e, image row y
+    int e = (int)(i / d.h) + 1, y = (int)(i % d.h);
+    int ly = y % T::TH;
+    int a = col_bit<T>(wk, d, e - 1, y, true), b = col_bit<T>(wk, d, e, y, false);
+    int c = -1, dd = -1;
+    if (ly > 0) {
+      c = col_bit<T>(wk, d, e - 1, y - 1, true);
+      dd = col_bit<T>(wk, d, e, y - 1, false);
+    }
+    if (a == b && !(ly > 0 && c == a && dd == b))
+      gunion(wk.gpar, col_node<T>(wk, d, e - 1, y, true), col_node<T>(wk, d, e, y, false));
+    if (ly > 0) {
+      if (b && c && !a && !dd) gunion(wk.gpar, col_node<T>(wk, d, e, y, false), col_node<T>(wk, d, e - 1, y - 1, true));
+      if (a && dd && !b && !c) gunion(wk.gpar, col_node<T>(wk, d, e - 1, y, true), col_node<T>(wk, d, e, y - 1, false));
+    }
+    return;
+  }
+  i -= nV;
+  if (i < 2 * (int64_t)nwr) {  // image top / bottom row: background runs join the exterior
+    bool bottom = i >= nwr;
+    int jw = (int)(i % nwr);
+    int row = bottom ? d.nty - 1 : 0;
+    u64 V = valid_mask(jw, d.w);
+    u64 bg = ~seam_bits<T>(wk, d, row, jw, bottom) & V;
+    u64 bgp = jw > 0 ? ~seam_bits<T>(wk, d, row, jw - 1, bottom) : 0ull;
+    u64 starts = bg & ~((bg << 1) | (bgp >> 63));
+    if (jw % T::WPR == 0) starts |= bg & 1ull;  // each tile holds its own piece
+    while (starts) {
+      int x = jw * 64 + __builtin_ctzll(starts);
+      starts &= starts - 1;
+      gunion(wk.gpar, seam_node<T>(wk, d, row, x, bottom), ext);
+    }
+    return;
+  }
+  i -= 2 * (int64_t)nwr;
+  if (i < 2 * (int64_t)d.h) {  // image left / right column
+    bool right = i >= d.h;
+    int y = (int)(i % d.h);
+    int tcol = right ? d.ntx - 1 : 0;
+    if (col_bit<T>(wk, d, tcol, y, right)) return;
+    if (y % T::TH > 0 && !col_bit<T>(wk, d, tcol, y - 1, right)) return;  // same piece as the row above
+    gunion(wk.gpar, col_node<T>(wk, d, tcol, y, right), ext);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K3: final roots; the root takes the minimum key and the feature sum
+
+template <class T, class Src>
+__global__ void __launch_bounds__(64) k_flatten(Src src, Work wk) {
+  const int64_t gt = blockIdx.x;
+  const ImgDesc& d = src.by_tile(gt);
+  const int64_t nbase = tile_node_base<T>(d, gt - d.tile0);
+  const int nb = wk.nbt[gt];
+  for (int i = threadIdx.x; i < nb; i += 64) {
+    int node = (int)(nbase + i);
+    int r = groot_ro(wk.gpar, node);
+    wk.gpar[node] = r;
+    if (r != node) {
+      atomicMin(&wk.gminkey[r], wk.gkey[node]);
+      Feature f = wk.gacc[node];
+      Feature* g = &wk.gacc[r];
+      atomicMin(&g->xmin, f.xmin);
+      atomicMax(&g->xmax, f.xmax);
+      atomicMin(&g->ymin, f.ymin);
+      atomicMax(&g->ymax, f.ymax);
+      atomicAdd(reinterpret_cast<unsigned long long*>(&g->S), (unsigned long long)f.S);
+      atomicAdd(reinterpret_cast<unsigned long long*>(&g->Sx), (unsigned long long)f.Sx);
+      atomicAdd(reinterpret_cast<unsigned long long*>(&g->Sy), (unsigned long long)f.Sy);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K4: leaders (node holding the component's first pixel) and their ranks
+
+template <class T, class Src>
+__global__ void __launch_bounds__(64) k_leaders(Src src, Work wk) {
+  __shared__ u16 pre[T::BCAP + 1];
+  __shared__ u32 first[T::TH];
+  __shared__ u32 cnt[T::TH];
+  const int64_t gt = blockIdx.x;
+  const ImgDesc& d = src.by_tile(gt);
+  const int64_t lt = gt - d.tile0;
+  const int tx = (int)(lt % d.ntx), ty = (int)(lt / d.ntx);
+  const int y0 = ty * T::TH;
+  const int th = d.h - y0 < T::TH ? d.h - y0 : T::TH;
+  const int64_t nbase = tile_node_base<T>(d, lt);
+  const int nb = wk.nbt[gt];
+  const int lane = threadIdx.x;
+  for (int ly = lane; ly < T::TH; ly += 64) {
+    first[ly] = 0xFFFFu;
+    cnt[ly] = 0;
+  }
+  __syncthreads();
+  u32 carry = 0;
+  for (int base = 0; base < nb; base += 64) {
+    int i = base + lane;
+    bool lead = false;
+    if (i < nb) {
+      int node = (int)(nbase + i);
+      int r = wk.gpar[node];
+      lead = r != (int)d.node0 && wk.gminkey[r] == wk.gkey[node];
+      int ly = (wk.grank[node] >> 16) & 63;
+      atomicMin(&first[ly], (u32)i);
+      if (lead) atomicAdd(&cnt[ly], 1u);
+    }
+    u64 bal = __ballot(lead);
+    if (i < nb) pre[i] = (u16)(carry + popc64(bal & low_mask(lane)));
+    carry += (u32)popc64(bal);
+  }
+  if (lane == 0) pre[nb] = (u16)carry;
+  __syncthreads();
+  for (int i = lane; i < nb; i += 64) {
+    int node = (int)(nbase + i);
+    int g = wk.grank[node];
+    int ly = (g >> 16) & 63;
+    int r = wk.gpar[node];
+    bool lead = r != (int)d.node0 && wk.gminkey[r] == wk.gkey[node];
+    int rank = (g & 0xFFFF) + (int)pre[i] - (int)pre[first[ly]];
+    wk.grank[node] = rank | (ly << 16) | (lead ? (int)HI : 0);
+  }
+  for (int ly = lane; ly < th; ly += 64) {
+    if (cnt[ly]) wk.cgrid[d.c0 + (int64_t)(y0 + ly) * d.ntx + tx] += (int)cnt[ly];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// scan of the count grid, per image: base = 1 + exclusive prefix
+
+__device__ inline u32 block_excl_scan(u32 v, u32* tmp, u32& total) {
+  // Hillis-Steele over SCAN_T threads in LDS
+  const int t = threadIdx.x;
+  tmp[t] = v;
+  __syncthreads();
+  for (int dlt = 1; dlt < SCAN_T; dlt <<= 1) {
+    u32 a = t >= dlt ? tmp[t - dlt] : 0u;
+    __syncthreads();
+    tmp[t] += a;
+    __syncthreads();
+  }
+  total = tmp[SCAN_T - 1];
+  u32 r = tmp[t] - v;
+  __syncthreads();
+  return r;
+}
+
+template <class Src>
+__global__ void __launch_bounds__(SCAN_T) k_scan_reduce(Src src, Work wk) {
+  __shared__ u32 tmp[SCAN_T];
+  const int64_t gb = blockIdx.x;
+  const ImgDesc& d = src.by_block(gb);
+  const int64_t n = (int64_t)d.h * d.ntx;
+  const int64_t b0 = (gb - d.blk0) * SCAN_B;
+  u32 v = 0;
+  for (int k = 0; k < 4; k++) {
+    int64_t e = b0 + threadIdx.x * 4 + k;
+    if (e < n) v += (u32)wk.cgrid[d.c0 + e];
+  }
+  u32 tot;
+  block_excl_scan(v, tmp, tot);
+  if (threadIdx.x == 0) wk.bsum[gb] = (int32_t)tot;
+}
+
+template <class Src>
+__global__ void __launch_bounds__(SCAN_T) k_scan_blocks(Src src, Work wk) {
+  __shared__ u32 tmp[SCAN_T];
+  const ImgDesc& d = src.by_index(blockIdx.x);
+  u32 carry = 0;
+  for (int base = 0; base < d.nblk; base += SCAN_T) {
+    int b = base + threadIdx.x;
+    u32 v = b < d.nblk ? (u32)wk.bsum[d.blk0 + b] : 0u;
+    u32 tot;
+    u32 ex = block_excl_scan(v, tmp, tot);
+    if (b < d.nblk) wk.bsum[d.blk0 + b] = (int32_t)(carry + ex);
+    carry += tot;
+  }
+  if (threadIdx.x == 0 && d.counts) d.counts[0] = 1 + (int64_t)carry;
+}
+
+template <class Src>
+__global__ void __launch_bounds__(SCAN_T) k_scan_apply(Src src, Work wk) {
+  __shared__ u32 tmp[SCAN_T];
+  const int64_t gb = blockIdx.x;
+  const ImgDesc& d = src.by_block(gb);
+  const int64_t n = (int64_t)d.h * d.ntx;
+  const int64_t b0 = (gb - d.blk0) * SCAN_B;
+  u32 v[4];
+  u32 sum = 0;
+  for (int k = 0; k < 4; k++) {
+    int64_t e = b0 + threadIdx.x * 4 + k;
+    v[k] = e < n ? (u32)wk.cgrid[d.c0 + e] : 0u;
+    sum += v[k];
+  }
+  u32 tot;
+  u32 ex = block_excl_scan(sum, tmp, tot) + (u32)wk.bsum[gb] + 1u;
+  for (int k = 0; k < 4; k++) {
+    int64_t e = b0 + threadIdx.x * 4 + k;
+    if (e < n) wk.cgrid[d.c0 + e] = (int32_t)ex;
+    ex += v[k];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K5: canonical ids and features of components that cross tiles
+
+template <class T, class Src>
+__global__ void __launch_bounds__(64) k_emit_border(Src src, Work wk) {
+  const int64_t gt = blockIdx.x;
+  const ImgDesc& d = src.by_tile(gt);
+  const int64_t lt = gt - d.tile0;
+  const int tx = (int)(lt % d.ntx), ty = (int)(lt / d.ntx);
+  const int y0 = ty * T::TH;
+  const int64_t nbase = tile_node_base<T>(d, lt);
+  const int nb = wk.nbt[gt];
+  if (lt == 0 && threadIdx.x == 0) {
+    wk.rcanon[d.node0] = 0;
+    if (d.feat) d.feat[0] = wk.gacc[d.node0];
+    if (d.parent) d.parent[0] = -1;
+    if (d.color) d.color[0] = 0;
+  }
+  for (int i = threadIdx.x; i < nb; i += 64) {
+    int node = (int)(nbase + i);
+    int g = wk.grank[node];
+    if (!(g & (int)HI)) continue;
+    int ly = (g >> 16) & 63;
+    int canon = wk.cgrid[d.c0 + (int64_t)(y0 + ly) * d.ntx + tx] + (g & 0xFFFF);
+    int r = wk.gpar[node];
+    wk.rcanon[r] = canon;
+    if (d.feat && canon < d.cap) d.feat[canon] = wk.gacc[r];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// K6: relabel the tile, write labels and the tables of the components it owns
+
+template <class T, class Src>
+__global__ void __launch_bounds__(256) k_tile_emit(Src src, Work wk) {
+  __shared__ TileSmem<T> s;
+  __shared__ Acc iacc[T::CAPI];
+  __shared__ int32_t bcanon[T::BCAP];
+  const int64_t gt = blockIdx.x;
+  const ImgDesc& d = src.by_tile(gt);
+  const int64_t lt = gt - d.tile0;
+  const int tx = (int)(lt % d.ntx), ty = (int)(lt / d.ntx);
+  const int x0 = tx * T::TW, y0 = ty * T::TH;
+  const int tw = d.w - x0 < T::TW ? d.w - x0 : T::TW;
+  const int th = d.h - y0 < T::TH ? d.h - y0 : T::TH;
+  const int tid = threadIdx.x;
+
+  tile_label<T>(s, d.img, d.pitch, x0, y0, tw, th, (d.flags & DF_VEC_IN) != 0);
+
+  const int64_t nbase = tile_node_base<T>(d, lt);
+  if (tid == 0) s.euler = 0;
+  // 8. canonical ids of border roots; leader mask (interior roots lead)
+  for (int wd = tid; wd < T::NW; wd += T::NT) s.lmask[wd] = s.rootm[wd] & ~s.bflag[wd];
+  __syncthreads();
+  for (int wd = tid; wd < T::NW; wd += T::NT) {
+    u64 bm = s.rootm[wd] & s.bflag[wd];
+    u64 lead = 0;
+    while (bm) {
+      int k = __builtin_ctzll(bm);
+      bm &= bm - 1;
+      int bi = s.bpre[wd] + popc64(s.rootm[wd] & s.bflag[wd] & low_mask(k));
+      int node = (int)(nbase + bi);
+      int r = wk.gpar[node];
+      bcanon[bi] = wk.rcanon[r];
+      if (wk.grank[node] & (int)HI) lead |= 1ull << k;
+    }
+    s.lmask[wd] |= lead;
+  }
+  __syncthreads();
+
+  // 9. canonical id into every root entry (HI marks a resolved entry)
+  int e_local = 0;
+  for (int wd = tid; wd < T::NW; wd += T::NT) {
+    int ly = wd / T::WPR, j = wd % T::WPR;
+    u64 rm = s.rootm[wd];
+    if (!rm) continue;
+    int rowlead = 0;
+    for (int jj = 0; jj < j; jj++) rowlead += popc64(s.lmask[ly * T::WPR + jj]);
+    int32_t base = wk.cgrid[d.c0 + (int64_t)(y0 + ly) * d.ntx + tx];
+    while (rm) {
+      int k = __builtin_ctzll(rm);
+      rm &= rm - 1;
+      int p = ly * T::TW + j * 64 + k;
+      int32_t canon;
+      if (s.bflag[wd] & (1ull << k)) canon = bcanon[bidx_of<T>(s, p)];
+      else canon = base + rowlead + popc64(s.lmask[wd] & low_mask(k));
+      if (s.lmask[wd] & (1ull << k)) e_local += ((s.bits[wd] >> k) & 1ull) ? 1 : -1;
+      s.par[p] = (u32)canon | HI;
+    }
+  }
+  __syncthreads();
+
+  // 10. features of interior components, CAPI at a time; their colour / parent
+  const int nint = s.nint;
+  for (int k0 = 0; k0 < nint; k0 += T::CAPI) {
+    for (int i = tid; i < T::CAPI; i += T::NT) acc_init(iacc[i]);
+    __syncthreads();
+    for (int c = tid; c < T::NCH; c += T::NT) {
+      int ly = c / T::CPR, cc = c % T::CPR;
+      if (ly >= th) continue;
+      for_segments<T>(s, ly, cc, tw, [&](int start, int a, int b) {
+        int p = ly * T::TW + start;
+        u32 v = s.par[p];
+        int r = (v & HI) ? p : (int)v;
+        if (s.bflag[r >> 6] & (1ull << (r & 63))) return;
+        int o = iord_of<T>(s, r) - k0;
+        if (o >= 0 && o < T::CAPI) acc_add(iacc[o], ly, a, b);
+      });
+    }
+    __syncthreads();
+    for (int wd = tid; wd < T::NW; wd += T::NT) {
+      int ly = wd / T::WPR, j = wd % T::WPR;
+      u64 im = s.rootm[wd] & ~s.bflag[wd];
+      while (im) {
+        int k = __builtin_ctzll(im);
+        im &= im - 1;
+        int p = ly * T::TW + j * 64 + k;
+        int o = iord_of<T>(s, p) - k0;
+        if (o < 0 || o >= T::CAPI) continue;
+        int32_t canon = (int32_t)(s.par[p] & ~HI);
+        if (canon >= d.cap) continue;
+        if (d.feat) d.feat[canon] = acc_abs(iacc[o], ly, x0, y0);
+        if (d.color) d.color[canon] = (u8)((s.bits[wd] >> k) & 1ull);
+        if (d.parent) {
+          int x = j * 64 + k;  // interior: x > 0
+          int q = ly * T::TW + run_start(s, ly, x - 1);
+          u32 v = s.par[q];
+          d.parent[canon] = (int32_t)(((v & HI) ? v : s.par[v]) & ~HI);
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // 11. colour / parent of border components whose first pixel is here
+  for (int wd = tid; wd < T::NW; wd += T::NT) {
+    int ly = wd / T::WPR, j = wd % T::WPR;
+    u64 bl = s.rootm[wd] & s.bflag[wd] & s.lmask[wd];
+    while (bl) {
+      int k = __builtin_ctzll(bl);
+      bl &= bl - 1;
+      int p = ly * T::TW + j * 64 + k;
+      int32_t canon = (int32_t)(s.par[p] & ~HI);
+      if (canon >= d.cap) continue;
+      if (d.color) d.color[canon] = (u8)((s.bits[wd] >> k) & 1ull);
+      if (d.parent) {
+        int x = j * 64 + k;
+        int32_t pc;
+        if (x > 0) {
+          int q = ly * T::TW + run_start(s, ly, x - 1);
+          u32 v = s.par[q];
+          pc = (int32_t)(((v & HI) ? v : s.par[v]) & ~HI);
+        } else if (tx > 0) {
+          int nl = col_node<T>(wk, d, tx - 1, y0 + ly, true);
+          pc = wk.rcanon[wk.gpar[nl]];
+        } else {
+          pc = 0;
+        }
+        d.parent[canon] = pc;
+      }
+    }
+  }
+  __syncthreads();
+
+  // 12. every run start takes its root's canonical id
+  for (int c = tid; c < T::NCH; c += T::NT) {
+    int ly = c / T::CPR, cc = c % T::CPR;
+    if (ly >= th) continue;
+    int j = cc >> 2, sh = (cc & 3) * 16;
+    u32 m = (u32)(s.st[ly * T::WPR + j] >> sh) & 0xFFFFu;
+    while (m) {
+      int p = ly * T::TW + j * 64 + sh + ctz32(m);
+      m &= m - 1;
+      u32 v = s.par[p];
+      if (!(v & HI)) s.par[p] = s.par[v];
+    }
+  }
+  atomicAdd(&s.euler, e_local);
+  __syncthreads();
+  if (tid == 0 && s.euler != 0 && d.counts)
+    atomicAdd(reinterpret_cast<unsigned long long*>(&d.counts[1]), (unsigned long long)(int64_t)s.euler);
+
+  // 13. label image, four pixels per thread
+  if (d.labels) {
+    const bool vec = (d.flags & DF_VEC_LAB) != 0;
+    for (int q = tid; q < T::TH * (T::TW / 4); q += T::NT) {
+      int ly = q / (T::TW / 4), x = (q % (T::TW / 4)) * 4;
+      if (ly >= th || x >= tw) continue;
+      int st0 = run_start(s, ly, x);
+      int32_t lab[4];
+      int32_t cur = (int32_t)(s.par[ly * T::TW + st0] & ~HI);
+      u64 sw = s.st[ly * T::WPR + (x >> 6)] >> (x & 63);
+      lab[0] = cur;
+      for (int k = 1; k < 4; k++) {
+        if ((sw >> k) & 1ull) cur = (int32_t)(s.par[ly * T::TW + x + k] & ~HI);
+        lab[k] = cur;
+      }
+      int32_t* dst = d.labels + (int64_t)(y0 + ly) * d.w + x0 + x;
+      if (vec && x + 4 <= tw) {
+        int4 v4;
+        v4.x = lab[0]; v4.y = lab[1]; v4.z = lab[2]; v4.w = lab[3];
+        *reinterpret_cast<int4*>(dst) = v4;
+      } else {
+        int n = tw - x < 4 ? tw - x : 4;
+        for (int k = 0; k < n; k++) dst[k] = lab[k];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side: workspace layout and the launch sequence
+
+struct Layout {
+  int64_t tiles, nodes, cells, blocks;
+  size_t off_gpar, off_gkey, off_gminkey, off_grank, off_rcanon, off_gacc, off_nbt;
+  size_t off_btop, off_bbot, off_bleft, off_bright, off_bitstop, off_bitsbot, off_bitslr;
+  size_t off_cgrid, off_bsum, bytes;
+};
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+template <class T>
+inline Layout make_layout(int64_t tiles, int64_t nodes, int64_t cells, int64_t blocks) {
+  Layout L;
+  L.tiles = tiles;
+  L.nodes = nodes;
+  L.cells = cells;
+  L.blocks = blocks;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes, 256);
+    return at;
+  };
+  L.off_gpar = take(4 * (size_t)nodes);
+  L.off_gkey = take(4 * (size_t)nodes);
+  L.off_gminkey = take(4 * (size_t)nodes);
+  L.off_grank = take(4 * (size_t)nodes);
+  L.off_rcanon = take(4 * (size_t)nodes);
+  L.off_gacc = take(sizeof(Feature) * (size_t)nodes);
+  L.off_nbt = take(4 * (size_t)tiles);
+  L.off_btop = take(2 * (size_t)tiles * T::TW);
+  L.off_bbot = take(2 * (size_t)tiles * T::TW);
+  L.off_bleft = take(2 * (size_t)tiles * T::TH);
+  L.off_bright = take(2 * (size_t)tiles * T::TH);
+  L.off_bitstop = take(8 * (size_t)tiles * T::WPR);
+  L.off_bitsbot = take(8 * (size_t)tiles * T::WPR);
+  L.off_bitslr = take(16 * (size_t)tiles);
+  L.off_cgrid = take(4 * (size_t)cells);
+  L.off_bsum = take(4 * (size_t)blocks);
+  L.bytes = o;
+  return L;
+}
+
+inline Work make_work(const Layout& L, void* ws) {
+  char* b = static_cast<char*>(ws);
+  Work w;
+  w.gpar = reinterpret_cast<int32_t*>(b + L.off_gpar);
+  w.gkey = reinterpret_cast<int32_t*>(b + L.off_gkey);
+  w.gminkey = reinterpret_cast<int32_t*>(b + L.off_gminkey);
+  w.grank = reinterpret_cast<int32_t*>(b + L.off_grank);
+  w.rcanon = reinterpret_cast<int32_t*>(b + L.off_rcanon);
+  w.gacc = reinterpret_cast<Feature*>(b + L.off_gacc);
+  w.nbt = reinterpret_cast<int32_t*>(b + L.off_nbt);
+  w.bidx_top = reinterpret_cast<u16*>(b + L.off_btop);
+  w.bidx_bot = reinterpret_cast<u16*>(b + L.off_bbot);
+  w.bidx_left = reinterpret_cast<u16*>(b + L.off_bleft);
+  w.bidx_right = reinterpret_cast<u16*>(b + L.off_bright);
+  w.bits_top = reinterpret_cast<u64*>(b + L.off_bitstop);
+  w.bits_bot = reinterpret_cast<u64*>(b + L.off_bitsbot);
+  w.bits_lr = reinterpret_cast<u64*>(b + L.off_bitslr);
+  w.cgrid = reinterpret_cast<int32_t*>(b + L.off_cgrid);
+  w.bsum = reinterpret_cast<int32_t*>(b + L.off_bsum);
+  return w;
+}
+
+// per-image geometry; fills the derived fields of d given running offsets
+template <class T>
+inline void place_image(ImgDesc& d, int64_t& tiles, int64_t& nodes, int64_t& cells, int64_t& blocks,
+                        int64_t& items) {
+  d.ntx = (d.w + T::TW - 1) / T::TW;
+  d.nty = (d.h + T::TH - 1) / T::TH;
+  int64_t nt = (int64_t)d.ntx * d.nty;
+  int64_t nc = (int64_t)d.h * d.ntx;
+  d.nblk = (int32_t)((nc + SCAN_B - 1) / SCAN_B);
+  d.tile0 = tiles;
+  d.node0 = nodes;
+  d.c0 = cells;
+  d.blk0 = blocks;
+  d.it0 = items;
+  d.nit = merge_items<T>(d.w, d.h, d.ntx, d.nty);
+  tiles += nt;
+  nodes += 1 + nt * T::BCAP;
+  cells += nc;
+  blocks += d.nblk;
+  items += d.nit;
+}
+
+// Enqueue the whole path.  `L` provides launch(kernel, grid, block, args...)
+// in stream order.  Every image's derived fields must come from place_image.
+template <class T, class Src, class Launcher>
+inline void enqueue(Launcher& L, const Src& src, const Work& wk, int64_t tiles, int64_t items, int64_t blocks,
+                    int64_t nimages) {
+  L.launch(k_tile_export<T, Src>, tiles, T::NT, src, wk);
+  if (items > 0) L.launch(k_border_merge<T, Src>, (items + 255) / 256, 256, src, wk, items);
+  L.launch(k_flatten<T, Src>, tiles, 64, src, wk);
+  L.launch(k_leaders<T, Src>, tiles, 64, src, wk);
+  L.launch(k_scan_reduce<Src>, blocks, SCAN_T, src, wk);
+  L.launch(k_scan_blocks<Src>, nimages, SCAN_T, src, wk);
+  L.launch(k_scan_apply<Src>, blocks, SCAN_T, src, wk);
+  L.launch(k_emit_border<T, Src>, tiles, 64, src, wk);
+  L.launch(k_tile_emit<T, Src>, tiles, T::NT, src, wk);
+}
+
+}  // namespace ccl

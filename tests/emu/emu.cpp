@@ -1,0 +1,292 @@
+// emu.cpp -- TEST HARNESS ONLY: runs the HIP kernels of ccl_pipeline.h on the
+// host (see hip_mock.h) for bounds checking and parity tests on small images.
+// Never part of the product: libccl.so is built from ccl.hip by hipcc.
+//
+// usage: ccl_emu <tile-config> <single|batch> <in.bin> <out.bin>
+//   in.bin : int32 n; then per image int32 w, h; int64 pitch; uint8 [h*pitch]
+//   out.bin: per image int64 n_labels, euler; int32 labels[h*w];
+//            then n_labels x (int64 xmin,xmax,ymin,ymax,S,Sx,Sy; int32 parent; int32 color)
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+#include <ucontext.h>
+
+#include <vector>
+
+#if defined(__SANITIZE_ADDRESS__)
+#include <sanitizer/common_interface_defs.h>
+#define EMU_ASAN 1
+#else
+#define EMU_ASAN 0
+#endif
+
+#include "../../paper_2006_09299_amd/csrc/ccl_pipeline.h"
+
+namespace {
+
+constexpr size_t STACK = 512 * 1024;
+enum { RUNNABLE, WAITING, DONE };
+
+struct Fiber {
+  ucontext_t ctx;
+  unsigned tid;
+  int state;
+  int wait_scope;  // 0: block, 1 + wave: wave
+  char* stack;
+};
+
+struct Sched {
+  ucontext_t main_ctx;
+  std::vector<Fiber> f;
+  std::vector<char*> stacks;
+  unsigned cur = 0;
+  emu_dim bidx{0, 0, 0}, bdim{1, 1, 1}, gdim{1, 1, 1};
+  std::function<void()> body;
+  unsigned long long xchg[16][64];
+  const void* main_stack_bottom = nullptr;
+  size_t main_stack_size = 0;
+} S;
+
+void* fake_main = nullptr;
+
+void fiber_entry() {
+#if EMU_ASAN
+  __sanitizer_finish_switch_fiber(nullptr, &S.main_stack_bottom, &S.main_stack_size);
+#endif
+  S.body();
+  Fiber& me = S.f[S.cur];
+  me.state = DONE;
+  S.xchg[me.tid / 64][me.tid % 64] = 0;
+#if EMU_ASAN
+  __sanitizer_start_switch_fiber(nullptr, S.main_stack_bottom, S.main_stack_size);
+#endif
+  swapcontext(&me.ctx, &S.main_ctx);
+}
+
+void yield_to_main() {
+  Fiber& me = S.f[S.cur];
+#if EMU_ASAN
+  void* fake = nullptr;
+  __sanitizer_start_switch_fiber(&fake, S.main_stack_bottom, S.main_stack_size);
+#endif
+  swapcontext(&me.ctx, &S.main_ctx);
+#if EMU_ASAN
+  __sanitizer_finish_switch_fiber(fake, &S.main_stack_bottom, &S.main_stack_size);
+#endif
+}
+
+void wait_on(int scope) {
+  Fiber& me = S.f[S.cur];
+  me.state = WAITING;
+  me.wait_scope = scope;
+  yield_to_main();
+}
+
+void run_block(unsigned block, unsigned nthreads) {
+  if (S.stacks.size() < nthreads) {
+    while (S.stacks.size() < nthreads) S.stacks.push_back(static_cast<char*>(malloc(STACK)));
+  }
+  S.f.assign(nthreads, Fiber());
+  S.bdim = emu_dim{nthreads, 1, 1};
+  S.bidx = emu_dim{block, 0, 0};
+  memset(S.xchg, 0, sizeof(S.xchg));
+  for (unsigned t = 0; t < nthreads; t++) {
+    Fiber& fb = S.f[t];
+    fb.tid = t;
+    fb.state = RUNNABLE;
+    fb.stack = S.stacks[t];
+    getcontext(&fb.ctx);
+    fb.ctx.uc_stack.ss_sp = fb.stack;
+    fb.ctx.uc_stack.ss_size = STACK;
+    fb.ctx.uc_link = nullptr;
+    makecontext(&fb.ctx, fiber_entry, 0);
+  }
+  const unsigned nwaves = (nthreads + 63) / 64;
+  for (;;) {
+    bool ran = false;
+    for (unsigned t = 0; t < nthreads; t++) {
+      if (S.f[t].state != RUNNABLE) continue;
+      S.cur = t;
+      ran = true;
+#if EMU_ASAN
+      void* fake = nullptr;
+      __sanitizer_start_switch_fiber(&fake, S.f[t].stack, STACK);
+#endif
+      swapcontext(&S.main_ctx, &S.f[t].ctx);
+#if EMU_ASAN
+      __sanitizer_finish_switch_fiber(fake, nullptr, nullptr);
+#endif
+    }
+    bool all_done = true;
+    for (auto& fb : S.f) all_done &= fb.state == DONE;
+    if (all_done) return;
+    if (ran) continue;
+    // release a barrier whose live members all wait on it
+    bool released = false;
+    for (int scope = 0; scope <= (int)nwaves && !released; scope++) {
+      bool any = false, all = true;
+      for (auto& fb : S.f) {
+        bool member = scope == 0 || (int)(fb.tid / 64) == scope - 1;
+        if (!member || fb.state == DONE) continue;
+        any = true;
+        if (!(fb.state == WAITING && fb.wait_scope == scope)) all = false;
+      }
+      if (any && all) {
+        for (auto& fb : S.f) {
+          bool member = scope == 0 || (int)(fb.tid / 64) == scope - 1;
+          if (member && fb.state == WAITING && fb.wait_scope == scope) fb.state = RUNNABLE;
+        }
+        released = true;
+      }
+    }
+    if (!released) {
+      fprintf(stderr, "emu: barrier deadlock in block %u\n", block);
+      abort();
+    }
+  }
+}
+
+struct EmuLauncher {
+  template <class... P, class... A>
+  void launch(void (*kernel)(P...), int64_t grid, int block, A... args) {
+    if (grid <= 0) return;
+    S.gdim = emu_dim{(unsigned)grid, 1, 1};
+    S.body = [&]() { kernel(args...); };
+    for (int64_t b = 0; b < grid; b++) run_block((unsigned)b, (unsigned)block);
+  }
+};
+
+}  // namespace
+
+emu_dim emu_thread_idx() { return emu_dim{S.f[S.cur].tid, 0, 0}; }
+emu_dim emu_block_idx() { return S.bidx; }
+emu_dim emu_block_dim() { return S.bdim; }
+emu_dim emu_grid_dim() { return S.gdim; }
+void emu_block_barrier() { wait_on(0); }
+void emu_wave_exchange(unsigned long long v, unsigned long long* all64) {
+  unsigned tid = S.f[S.cur].tid;
+  unsigned wave = tid / 64;
+  S.xchg[wave][tid % 64] = v;
+  wait_on(1 + (int)wave);
+  memcpy(all64, S.xchg[wave], sizeof(unsigned long long) * 64);
+  wait_on(1 + (int)wave);
+}
+
+namespace {
+
+struct Image {
+  int32_t w, h;
+  int64_t pitch;
+  std::vector<uint8_t> data;
+  // outputs
+  std::vector<int32_t> labels;
+  std::vector<ccl::Feature> feat;
+  std::vector<int32_t> parent;
+  std::vector<uint8_t> color;
+  int64_t counts[2];
+};
+
+template <class T>
+void run_images(std::vector<Image>& ims, bool batch) {
+  for (auto& im : ims) {
+    int64_t cap = (int64_t)im.w * im.h + 1;
+    im.labels.assign((size_t)im.w * im.h, -7);
+    im.feat.assign((size_t)cap, ccl::Feature{-7, -7, -7, -7, -7, -7, -7});
+    im.parent.assign((size_t)cap, -7);
+    im.color.assign((size_t)cap, 7);
+    im.counts[0] = im.counts[1] = -7;
+  }
+  auto desc_of = [](Image& im) {
+    ccl::ImgDesc d;
+    memset(&d, 0, sizeof(d));
+    d.img = im.data.data();
+    d.pitch = im.pitch;
+    d.w = im.w;
+    d.h = im.h;
+    d.labels = im.labels.data();
+    d.feat = im.feat.data();
+    d.parent = im.parent.data();
+    d.color = im.color.data();
+    d.cap = (int64_t)im.w * im.h + 1;
+    d.counts = im.counts;
+    d.flags = 0;
+    if ((reinterpret_cast<uintptr_t>(d.img) & 15) == 0 && (d.pitch & 15) == 0) d.flags |= ccl::DF_VEC_IN;
+    if ((reinterpret_cast<uintptr_t>(d.labels) & 15) == 0 && (d.w & 3) == 0) d.flags |= ccl::DF_VEC_LAB;
+    return d;
+  };
+  EmuLauncher L;
+  auto run = [&](std::vector<ccl::ImgDesc>& ds) {
+    int64_t tiles = 0, nodes = 0, cells = 0, blocks = 0, items = 0;
+    for (auto& d : ds) ccl::place_image<T>(d, tiles, nodes, cells, blocks, items);
+    ccl::Layout lay = ccl::make_layout<T>(tiles, nodes, cells, blocks);
+    std::vector<unsigned char> ws(lay.bytes);
+    memset(ws.data(), 0xA5, ws.size());  // garbage: the path must not rely on zeroed scratch
+    ccl::Work wk = ccl::make_work(lay, ws.data());
+    if (ds.size() == 1 && !batch) {
+      ccl::OneImage src{ds[0]};
+      ccl::enqueue<T>(L, src, wk, tiles, items, blocks, 1);
+    } else {
+      ccl::ManyImages src{ds.data(), (int32_t)ds.size()};
+      ccl::enqueue<T>(L, src, wk, tiles, items, blocks, (int64_t)ds.size());
+    }
+  };
+  if (batch) {
+    std::vector<ccl::ImgDesc> ds;
+    for (auto& im : ims) ds.push_back(desc_of(im));
+    run(ds);
+  } else {
+    for (auto& im : ims) {
+      std::vector<ccl::ImgDesc> ds{desc_of(im)};
+      run(ds);
+    }
+  }
+}
+
+}  // namespace
+
+int main(int argc, char** argv) {
+  if (argc != 5) {
+    fprintf(stderr, "usage: %s <tile-config> <single|batch> <in.bin> <out.bin>\n", argv[0]);
+    return 2;
+  }
+  FILE* fi = fopen(argv[3], "rb");
+  if (!fi) return 3;
+  int32_t n = 0;
+  if (fread(&n, 4, 1, fi) != 1) return 3;
+  std::vector<Image> ims((size_t)n);
+  for (auto& im : ims) {
+    if (fread(&im.w, 4, 1, fi) != 1 || fread(&im.h, 4, 1, fi) != 1 || fread(&im.pitch, 8, 1, fi) != 1) return 3;
+    // 16-byte aligned rows when the pitch allows it (the vector path), else not
+    im.data.resize((size_t)im.h * im.pitch);
+    if (fread(im.data.data(), 1, im.data.size(), fi) != im.data.size()) return 3;
+  }
+  fclose(fi);
+  bool batch = strcmp(argv[2], "batch") == 0;
+  int cfg = atoi(argv[1]);
+  switch (cfg) {
+    case 0: run_images<ccl::Tile<32, 128>>(ims, batch); break;
+    case 1: run_images<ccl::Tile<4, 64>>(ims, batch); break;
+    case 2: run_images<ccl::Tile<3, 64>>(ims, batch); break;
+    case 3: run_images<ccl::Tile<5, 192>>(ims, batch); break;
+    case 4: run_images<ccl::Tile<64, 64>>(ims, batch); break;
+    case 5: run_images<ccl::Tile<1, 64>>(ims, batch); break;
+    default: fprintf(stderr, "bad tile config\n"); return 2;
+  }
+  FILE* fo = fopen(argv[4], "wb");
+  if (!fo) return 4;
+  for (auto& im : ims) {
+    fwrite(im.counts, 8, 2, fo);
+    fwrite(im.labels.data(), 4, im.labels.size(), fo);
+    int64_t nl = im.counts[0];
+    if (nl < 0 || nl > (int64_t)im.feat.size()) nl = 0;
+    for (int64_t k = 0; k < nl; k++) {
+      const ccl::Feature& f = im.feat[(size_t)k];
+      int64_t v[7] = {f.xmin, f.xmax, f.ymin, f.ymax, f.S, f.Sx, f.Sy};
+      fwrite(v, 8, 7, fo);
+      int32_t pc[2] = {im.parent[(size_t)k], (int32_t)im.color[(size_t)k]};
+      fwrite(pc, 4, 2, fo);
+    }
+  }
+  fclose(fo);
+  return 0;
+}

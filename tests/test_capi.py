@@ -1,0 +1,80 @@
+"""Host-side checks of the C-ABI library (no GPU compute): it loads, exports
+every symbol include/ccl.h declares, and rejects bad arguments on the host."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2006_09299_amd import _capi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    txt = open(os.path.join(ROOT, "include", "ccl.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ccl_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_declares_exports():
+    assert _declared_functions() == sorted(_capi.EXPORTS)
+
+
+def test_library_exports_every_symbol():
+    L = _capi.lib()
+    for name in _declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_strerror_and_tile_shape():
+    assert _capi.strerror(0) == "ok"
+    assert "workspace" in _capi.strerror(_capi.CCL_ENOSPC)
+    th, tw = _capi.tile_shape()
+    assert th >= 1 and tw % 64 == 0
+
+
+def test_workspace_bytes_pure_and_monotone():
+    a = _capi.workspace_bytes(512, 512)
+    assert a > 0 and a == _capi.workspace_bytes(512, 512)
+    assert _capi.workspace_bytes(1024, 512) > a
+    assert _capi.workspace_bytes(0, 5) == 0 and _capi.workspace_bytes(5, -1) == 0
+
+
+def _call(img, w, h, pitch, out, ws, wsb):
+    return _capi.lib().ccl_label(img, w, h, pitch, ctypes.byref(out) if out is not None else None, ws, wsb, None)
+
+
+def test_label_rejects_bad_arguments_on_host():
+    fake = 0x1000  # never dereferenced: every case fails validation first
+    out = _capi.ccl_outputs_t(fake, fake, fake, fake, 10, fake)
+    wsb = _capi.workspace_bytes(64, 64)
+    E = _capi.CCL_EINVAL
+    assert _call(None, 64, 64, 64, out, fake, wsb) == E
+    assert _call(fake, 0, 64, 64, out, fake, wsb) == E
+    assert _call(fake, 64, -1, 64, out, fake, wsb) == E
+    assert _call(fake, 64, 64, 63, out, fake, wsb) == E
+    assert _call(fake, 64, 64, 64, None, fake, wsb) == E
+    assert _call(fake, 64, 64, 64, out, None, wsb) == E
+    assert _call(fake, 65536, 65536, 65536, out, fake, 1 << 40) == E  # w*h >= 2^31-1
+    bad_cap = _capi.ccl_outputs_t(fake, fake, fake, fake, 0, fake)
+    assert _call(fake, 64, 64, 64, bad_cap, fake, wsb) == E
+    no_counts = _capi.ccl_outputs_t(fake, fake, fake, fake, 10, None)
+    assert _call(fake, 64, 64, 64, no_counts, fake, wsb) == E
+    assert _call(fake, 64, 64, 64, out, fake, wsb - 1) == _capi.CCL_ENOSPC
+
+
+def test_batch_sizes_and_prepare_on_host():
+    fake = 0x1000
+    imgs = (_capi.ccl_image_t * 3)()
+    for i, (w, h) in enumerate([(64, 64), (100, 33), (1, 1)]):
+        imgs[i] = _capi.ccl_image_t(fake, w, h, w, _capi.ccl_outputs_t(fake, fake, fake, fake, 8, fake))
+    db, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    assert _capi.lib().ccl_batch_sizes(imgs, 3, ctypes.byref(db), ctypes.byref(wb)) == 0
+    assert db.value > 0 and wb.value >= _capi.workspace_bytes(64, 64)
+    host = (ctypes.c_char * db.value)()
+    assert _capi.lib().ccl_batch_prepare(imgs, 3, host, db.value) == 0
+    assert _capi.lib().ccl_batch_prepare(imgs, 3, host, db.value - 1) == _capi.CCL_EINVAL
+    imgs[1].pitch = 10  # < w
+    assert _capi.lib().ccl_batch_sizes(imgs, 3, ctypes.byref(db), ctypes.byref(wb)) == _capi.CCL_EINVAL
+    assert _capi.lib().ccl_label_batch(imgs, 0, host, host, 1, None) == _capi.CCL_EINVAL
