@@ -40,7 +40,7 @@ EXPORTS = (
     "ccl_workspace_bytes", "ccl_label", "ccl_label_traced", "ccl_kernel_name", "ccl_batch_sizes",
     "ccl_batch_prepare", "ccl_label_batch", "ccl_strerror", "ccl_tile_shape",
 )
-TRACE_EVENTS = 10
+TRACE_EVENTS = 11
 
 _lib = None
 

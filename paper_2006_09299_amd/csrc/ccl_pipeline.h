@@ -28,8 +28,9 @@
 //                   vertical seams, foreground diagonals across corners) and
 //                   background on the image border with the exterior node,
 //                   atomicMin union-find in HBM.
-//   k_flatten     : final root of every border node; root takes the minimum
-//                   raster key and the sum of the partial features.
+//   k_flatten     : final root of every border node (full path compression).
+//   k_reduce_roots: the root takes the minimum raster key and the sum of the
+//                   partial features (LDS hash per group of tiles first).
 //   k_leaders     : which border node holds its component's first pixel; rank
 //                   of that pixel among the components starting in the same
 //                   row of the same tile.
@@ -186,15 +187,24 @@ __device__ inline u32 lroot(const u32* par, u32 x) {
 }
 
 // Union-find in HBM over border nodes (same scheme, agent scope).
+// Find with full path compression: every entry on the walked path is pointed
+// at the root found.  During concurrent unions that root may be linked
+// further, so the write is still an ancestor; once no union runs, all writes
+// of one class carry the same (final) root.
 __device__ inline int gfind(int32_t* gp, int x) {
-  for (;;) {
-    int p = ld_ag(&gp[x]);
-    if (p == x) return x;
-    int g = ld_ag(&gp[p]);
-    if (g == p) return p;
-    st_ag(&gp[x], g);
-    x = g;
+  int r = x;
+  int p = ld_ag(&gp[r]);
+  while (p != r) {
+    r = p;
+    p = ld_ag(&gp[r]);
   }
+  while (x != r) {
+    int n = ld_ag(&gp[x]);
+    if (n == r) break;
+    st_ag(&gp[x], r);
+    x = n;
+  }
+  return r;
 }
 __device__ inline void gunion(int32_t* gp, int a, int b) {
   for (;;) {
@@ -206,11 +216,6 @@ __device__ inline void gunion(int32_t* gp, int a, int b) {
     if (old == b) return;
     b = old;
   }
-}
-__device__ inline int groot_ro(const int32_t* gp, int x) {
-  int p = ld_ag(&gp[x]);
-  while (p != x) { x = p; p = ld_ag(&gp[x]); }
-  return x;
 }
 
 // Pixel pairs of two consecutive rows that unite runs (B&W unification).
@@ -771,7 +776,13 @@ __global__ void __launch_bounds__(256) k_border_merge(Src src, Work wk, int64_t 
 }
 
 // ---------------------------------------------------------------------------
-// K3: final roots; the root takes the minimum key and the feature sum
+// K3: final roots.  k_flatten points every border node at its root;
+// k_reduce_roots then adds the partial features (and minimum key) of every
+// non-root node into its root.  To keep the number of global atomics on the
+// accumulators of components spanning many tiles (the exterior, percolating
+// clusters) small, a workgroup first merges the contributions of a group of
+// consecutive tiles in an LDS hash table keyed by root and issues one set of
+// atomics per root per flush.
 
 template <class T, class Src>
 __global__ void __launch_bounds__(64) k_flatten(Src src, Work wk) {
@@ -781,19 +792,104 @@ __global__ void __launch_bounds__(64) k_flatten(Src src, Work wk) {
   const int nb = wk.nbt[gt];
   for (int i = threadIdx.x; i < nb; i += 64) {
     int node = (int)(nbase + i);
-    int r = groot_ro(wk.gpar, node);
-    wk.gpar[node] = r;
-    if (r != node) {
-      atomicMin(&wk.gminkey[r], wk.gkey[node]);
-      Feature f = wk.gacc[node];
-      Feature* g = &wk.gacc[r];
-      atomicMin(&g->xmin, f.xmin);
-      atomicMax(&g->xmax, f.xmax);
-      atomicMin(&g->ymin, f.ymin);
-      atomicMax(&g->ymax, f.ymax);
-      atomicAdd(reinterpret_cast<unsigned long long*>(&g->S), (unsigned long long)f.S);
-      atomicAdd(reinterpret_cast<unsigned long long*>(&g->Sx), (unsigned long long)f.Sx);
-      atomicAdd(reinterpret_cast<unsigned long long*>(&g->Sy), (unsigned long long)f.Sy);
+    int r = gfind(wk.gpar, node);
+    st_ag(&wk.gpar[node], r);
+  }
+}
+
+constexpr int RH_CAP = 1024;     // LDS hash slots
+constexpr int RH_TILES = 16;     // tiles per workgroup
+constexpr int RH_T = 256;        // threads
+constexpr int RH_EMPTY = -1;
+
+struct RootAcc {
+  int32_t key, minkey;
+  int32_t xmin, xmax, ymin, ymax;
+  u64 S, Sx, Sy;
+};
+
+__device__ inline void rootacc_clear(RootAcc& a) {
+  a.key = RH_EMPTY;
+  a.minkey = 0x7FFFFFFF;
+  a.xmin = 0x7FFFFFFF;
+  a.xmax = -1;
+  a.ymin = 0x7FFFFFFF;
+  a.ymax = -1;
+  a.S = a.Sx = a.Sy = 0;
+}
+
+template <class T, class Src>
+__global__ void __launch_bounds__(RH_T) k_reduce_roots(Src src, Work wk, int64_t tiles) {
+  __shared__ RootAcc tab[RH_CAP];
+  __shared__ int used;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < RH_CAP; i += RH_T) rootacc_clear(tab[i]);
+  if (tid == 0) used = 0;
+  __syncthreads();
+  const int64_t t0 = (int64_t)blockIdx.x * RH_TILES;
+  const int64_t t1 = t0 + RH_TILES < tiles ? t0 + RH_TILES : tiles;
+  // nodes of the group, enumerated tile by tile in chunks of RH_T
+  int64_t gt = t0;
+  int base = 0;
+  while (gt < t1) {
+    const ImgDesc& d = src.by_tile(gt);
+    const int nb = wk.nbt[gt];
+    const int64_t nbase = tile_node_base<T>(d, gt - d.tile0);
+    int i = base + tid;
+    if (i < nb) {
+      int node = (int)(nbase + i);
+      int r = wk.gpar[node];
+      if (r != node) {
+        uint32_t hsh = ((uint32_t)r * 2654435761u) >> 22;  // 10 bits
+        int slot = (int)hsh;
+        for (;;) {
+          int k = atomicCAS(&tab[slot].key, RH_EMPTY, r);
+          if (k == RH_EMPTY) {
+            atomicAdd(&used, 1);
+            break;
+          }
+          if (k == r) break;
+          slot = (slot + 1) & (RH_CAP - 1);
+        }
+        RootAcc& a = tab[slot];
+        Feature f = wk.gacc[node];
+        atomicMin(&a.minkey, wk.gkey[node]);
+        atomicMin(&a.xmin, f.xmin);
+        atomicMax(&a.xmax, f.xmax);
+        atomicMin(&a.ymin, f.ymin);
+        atomicMax(&a.ymax, f.ymax);
+        atomicAdd(&a.S, (u64)f.S);
+        atomicAdd(&a.Sx, (u64)f.Sx);
+        atomicAdd(&a.Sy, (u64)f.Sy);
+      }
+    }
+    base += RH_T;
+    if (base >= nb) {
+      base = 0;
+      gt++;
+    }
+    __syncthreads();
+    // flush when another chunk might not fit, and at the end
+    const bool flush = used > RH_CAP - RH_T || gt >= t1;
+    if (flush) {
+      for (int j = tid; j < RH_CAP; j += RH_T) {
+        RootAcc& a = tab[j];
+        if (a.key == RH_EMPTY) continue;
+        int r = a.key;
+        atomicMin(&wk.gminkey[r], a.minkey);
+        Feature* g = &wk.gacc[r];
+        atomicMin(&g->xmin, a.xmin);
+        atomicMax(&g->xmax, a.xmax);
+        atomicMin(&g->ymin, a.ymin);
+        atomicMax(&g->ymax, a.ymax);
+        atomicAdd(reinterpret_cast<unsigned long long*>(&g->S), (unsigned long long)a.S);
+        atomicAdd(reinterpret_cast<unsigned long long*>(&g->Sx), (unsigned long long)a.Sx);
+        atomicAdd(reinterpret_cast<unsigned long long*>(&g->Sy), (unsigned long long)a.Sy);
+        rootacc_clear(a);
+      }
+      __syncthreads();
+      if (tid == 0) used = 0;
+      __syncthreads();
     }
   }
 }
@@ -1235,6 +1331,7 @@ inline void enqueue(Launcher& L, const Src& src, const Work& wk, int64_t tiles, 
   L.launch(k_tile_export<T, Src>, tiles, T::NT, src, wk);
   if (items > 0) L.launch(k_border_merge<T, Src>, (items + 255) / 256, 256, src, wk, items);
   L.launch(k_flatten<T, Src>, tiles, 64, src, wk);
+  L.launch(k_reduce_roots<T, Src>, (tiles + RH_TILES - 1) / RH_TILES, RH_T, src, wk, tiles);
   L.launch(k_leaders<T, Src>, tiles, 64, src, wk);
   L.launch(k_scan_reduce<Src>, blocks, SCAN_T, src, wk);
   L.launch(k_scan_blocks<Src>, nimages, SCAN_T, src, wk);

@@ -114,6 +114,12 @@ inline P atomicAdd(P* p, V v) {
   *p = (P)(old + (P)v);
   return old;
 }
+template <class P, class V, class W>
+inline P atomicCAS(P* p, V cmp, W v) {
+  P old = *p;
+  if (old == (P)cmp) *p = (P)v;
+  return old;
+}
 template <class P, class V>
 inline P atomicOr(P* p, V v) {
   P old = *p;

@@ -49,7 +49,10 @@ def test_emulated_kernels_batched_padded_pitch():
 
 
 def test_emulated_kernels_production_tile():
-    imgs = _cases(11, 4, 80, 400) + [synth.bernoulli_blocks(70, 300, 0.5, 1, 5)]
+    # the dense 128 x 2048 image fills the root-reduction hash of a tile group
+    # more than once (flush while scanning, then at the end)
+    imgs = _cases(11, 4, 80, 400) + [synth.bernoulli_blocks(70, 300, 0.5, 1, 5),
+                                     synth.bernoulli_blocks(128, 2048, 0.5, 1, 3)]
     for img, r in zip(imgs, emu_runner.run(imgs, tile_cfg=0, pitch_pad=16)):
         _assert_same(img, r)
 
