@@ -187,10 +187,14 @@ __device__ inline u32 lroot(const u32* par, u32 x) {
 }
 
 // Union-find in HBM over border nodes (same scheme, agent scope).
-// Find with full path compression: every entry on the walked path is pointed
-// at the root found.  During concurrent unions that root may be linked
-// further, so the write is still an ancestor; once no union runs, all writes
-// of one class carry the same (final) root.
+// Find with path compression.  Every entry points to a smaller index unless
+// it is a root, so both walks strictly decrease and end.  The second walk
+// points the entries above the root found at that root.  Concurrent unions
+// may link that root (or entries of the path) to smaller indices meanwhile:
+// the walk stops as soon as it reaches an index <= r and only ever writes r
+// into an entry x > r, an ancestor of x, so no write can raise an entry,
+// touch a root or close a cycle.  Without concurrent unions all writes of a
+// class carry its final root.
 __device__ inline int gfind(int32_t* gp, int x) {
   int r = x;
   int p = ld_ag(&gp[r]);
@@ -198,9 +202,9 @@ __device__ inline int gfind(int32_t* gp, int x) {
     r = p;
     p = ld_ag(&gp[r]);
   }
-  while (x != r) {
+  while (x > r) {
     int n = ld_ag(&gp[x]);
-    if (n == r) break;
+    if (n <= r) break;
     st_ag(&gp[x], r);
     x = n;
   }
