@@ -189,12 +189,18 @@ __device__ inline u32 lroot(const u32* par, u32 x) {
 // Union-find in HBM over border nodes (same scheme, agent scope).
 // Find with path compression.  Every entry points to a smaller index unless
 // it is a root, so both walks strictly decrease and end.  The second walk
-// points the entries above the root found at that root.  Concurrent unions
-// may link that root (or entries of the path) to smaller indices meanwhile:
-// the walk stops as soon as it reaches an index <= r and only ever writes r
-// into an entry x > r, an ancestor of x, so no write can raise an entry,
-// touch a root or close a cycle.  Without concurrent unions all writes of a
-// class carry its final root.
+// points the entries above the root found at that root.
+// Concurrency with unions: a union that finds a stale root b performs
+// atomicMin on gp[b] anyway, which moves b's subtree under another tree until
+// the same union re-merges it; so the second walk may pass into a tree whose
+// root is not r.  Writing into an entry that is a root at that moment would
+// overwrite a link another union has just made (and counts as done), losing
+// that union.  The walk therefore only writes into entries it has just read
+// as non-roots (n != x), only ever writes r < x (an ancestor, or a member of a
+// tree that the pending union is about to merge with), and stops at the first
+// index <= r.  A non-root never becomes a root again, so such a write cannot
+// meet a successful link.  Without concurrent unions all writes of a class
+// carry its final root.
 __device__ inline int gfind(int32_t* gp, int x) {
   int r = x;
   int p = ld_ag(&gp[r]);
@@ -204,7 +210,7 @@ __device__ inline int gfind(int32_t* gp, int x) {
   }
   while (x > r) {
     int n = ld_ag(&gp[x]);
-    if (n <= r) break;
+    if (n <= r || n == x) break;
     st_ag(&gp[x], r);
     x = n;
   }

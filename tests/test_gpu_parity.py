@@ -187,7 +187,28 @@ def test_deterministic_repeats():
         assert torch.equal(r.parent, ref.parent) and torch.equal(r.color, ref.color)
 
 
-SWEEP_FULL = [(0.1, 1), (0.5, 1), (0.9, 1), (0.5, 4), (0.3, 16)]
+@pytest.mark.parametrize("p,g,seed,reps", [(0.3, 4, 111, 6), (0.5, 1, 102, 4), (0.7, 2, 108, 4)])
+def test_repeated_full_size_runs_agree_with_oracle(p, g, seed, reps):
+    """Races in the union-find show up as run-to-run differences in the
+    number of components: compare every repetition with the oracle."""
+    img = synth.bernoulli_blocks(8192, 8192, p, g, seed)
+    o = oracle.label(img)
+    t = torch.from_numpy(img).to(_dev())
+    ccl = _lib()
+    first = None
+    for k in range(reps):
+        r = ccl.label(t, cap=o.n_labels)
+        torch.cuda.synchronize()
+        _say("repeat", p, g, k, r.n_labels, r.euler)
+        assert (r.n_labels, r.euler) == (o.n_labels, o.euler)
+        if first is None:
+            first = r
+            _assert_same(r, o)
+        else:
+            assert torch.equal(r.labels, first.labels) and torch.equal(r.features, first.features)
+
+
+SWEEP_FULL = [(0.1, 1), (0.5, 1), (0.9, 1), (0.5, 4), (0.3, 4), (0.3, 16)]
 
 
 @pytest.mark.parametrize("p,g", [(p, g) for g in synth.SWEEP_G for p in synth.SWEEP_P])
