@@ -156,8 +156,9 @@ __device__ inline int ld_ag(const int32_t* p) { return __hip_atomic_load(p, __AT
 __device__ inline void st_ag(int32_t* p, int v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 
 // Union-find in LDS over tile positions: union by minimum, path halving.
-// Path halving only ever writes an ancestor, and a successful link needs the
-// linked entry to still be a root, so concurrent finds and links are safe.
+// A root is linked with compare-and-swap only while it is still a root, so a
+// tree never loses members; path halving only ever writes an ancestor into a
+// non-root.  Concurrent finds and links are therefore safe.
 __device__ inline u32 lfind(u32* par, u32 x) {
   for (;;) {
     u32 p = ld_wg(&par[x]);
@@ -174,9 +175,7 @@ __device__ inline void lunion(u32* par, u32 a, u32 b) {
     b = lfind(par, b);
     if (a == b) return;
     if (a > b) { u32 t = a; a = b; b = t; }
-    u32 old = __hip_atomic_fetch_min(&par[b], a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    if (old == b) return;
-    b = old;  // b had been linked meanwhile: unite a with its parent
+    if (atomicCAS(&par[b], b, a) == b) return;  // else b was linked meanwhile: retry
   }
 }
 // read-only walk to the root (no writes)
@@ -190,16 +189,12 @@ __device__ inline u32 lroot(const u32* par, u32 x) {
 // Find with path compression.  Every entry points to a smaller index unless
 // it is a root, so both walks strictly decrease and end.  The second walk
 // points the entries above the root found at that root.
-// Concurrency with unions: a union that finds a stale root b performs
-// atomicMin on gp[b] anyway, which moves b's subtree under another tree until
-// the same union re-merges it; so the second walk may pass into a tree whose
-// root is not r.  Writing into an entry that is a root at that moment would
-// overwrite a link another union has just made (and counts as done), losing
-// that union.  The walk therefore only writes into entries it has just read
-// as non-roots (n != x), only ever writes r < x (an ancestor, or a member of a
-// tree that the pending union is about to merge with), and stops at the first
-// index <= r.  A non-root never becomes a root again, so such a write cannot
-// meet a successful link.  Without concurrent unions all writes of a class
+// Concurrency with unions (gunion): roots are linked by compare-and-swap only
+// while they are roots, so trees only grow and the root found stays an
+// ancestor of every entry of the walked path.  The walk writes only into
+// entries it has just read as non-roots (a non-root never becomes a root
+// again, so no write can meet a link), only ever writes r < x, and stops at
+// the first index <= r.  Without concurrent unions all writes of a class
 // carry its final root.
 __device__ inline int gfind(int32_t* gp, int x) {
   int r = x;
@@ -222,9 +217,10 @@ __device__ inline void gunion(int32_t* gp, int a, int b) {
     b = gfind(gp, b);
     if (a == b) return;
     if (a > b) { int t = a; a = b; b = t; }
-    int old = __hip_atomic_fetch_min(&gp[b], a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (old == b) return;
-    b = old;
+    // link the larger root under the smaller one, only if it is still a root
+    if (__hip_atomic_compare_exchange_strong(&gp[b], &b, a, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT))
+      return;
   }
 }
 

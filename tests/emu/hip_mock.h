@@ -80,6 +80,7 @@ inline unsigned long long __ballot(int pred) {
 #define __hip_atomic_load emu_atomic_load
 #define __hip_atomic_store emu_atomic_store
 #define __hip_atomic_fetch_min emu_atomic_fetch_min
+#define __hip_atomic_compare_exchange_strong emu_atomic_cas
 
 template <class P>
 inline P emu_atomic_load(const P* p, int, int) {
@@ -94,6 +95,16 @@ inline P emu_atomic_fetch_min(P* p, V v, int, int) {
   P old = *p;
   if ((P)v < old) *p = (P)v;
   return old;
+}
+
+template <class P, class V>
+inline bool emu_atomic_cas(P* p, P* expected, V desired, int, int, int) {
+  if (*p == *expected) {
+    *p = (P)desired;
+    return true;
+  }
+  *expected = *p;
+  return false;
 }
 
 template <class P, class V>
