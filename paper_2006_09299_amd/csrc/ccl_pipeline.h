@@ -307,7 +307,7 @@ template <class T>
 __device__ void tile_label(TileSmem<T>& s, const u8* img, int64_t pitch, int x0, int y0, int tw, int th,
                            bool vec_in) {
   const int tid = threadIdx.x;
-  // 1. load bytes, 16 pixels per chunk -> 16 bits; par[p] = p
+  // 1. load bytes, 16 pixels per chunk -> 16 bits
   for (int c = tid; c < T::NCH; c += T::NT) {
     int ly = c / T::CPR, cx = (c % T::CPR) * 16;
     u32 m = 0;
@@ -323,26 +323,39 @@ __device__ void tile_label(TileSmem<T>& s, const u8* img, int64_t pitch, int x0,
     }
     reinterpret_cast<u16*>(s.bits)[c] = (u16)m;
   }
-  for (int i = tid; i < T::N; i += T::NT) s.par[i] = (u32)i;
   for (int i = tid; i < T::NW; i += T::NT) s.bflag[i] = 0;
   __syncthreads();
 
-  // 2. run starts per row; last start per word
+  // 2. run starts, 16 pixels per chunk; par[p] = p at every run start (the
+  // only entries ever read); last start per word, one row per thread
+  for (int c = tid; c < T::NCH; c += T::NT) {
+    int ly = c / T::CPR, cc = c % T::CPR;
+    const u16* b16 = reinterpret_cast<const u16*>(s.bits);
+    u32 b = b16[c];
+    u32 carry = cc ? (u32)(b16[c - 1] >> 15) : (~b & 1u);
+    u32 e = (b ^ ((b << 1) | carry)) & (u32)valid_mask(0, tw - cc * 16) & 0xFFFFu;
+    if (ly >= th) e = 0;
+    reinterpret_cast<u16*>(s.st)[c] = (u16)e;
+    const u32 p0 = (u32)(ly * T::TW + cc * 16);
+    while (e) {
+      u32 p = p0 + (u32)ctz32(e);
+      e &= e - 1;
+      s.par[p] = p;
+    }
+  }
   for (int ly = tid; ly < T::TH; ly += T::NT) {
     int lastx = 0;
     for (int j = 0; j < T::WPR; j++) {
       u64 b = s.bits[ly * T::WPR + j];
       u64 carry = j ? (s.bits[ly * T::WPR + j - 1] >> 63) : (~b & 1ull);
       u64 e = (b ^ ((b << 1) | carry)) & valid_mask(j, tw);
-      if (ly >= th) e = 0;
-      s.st[ly * T::WPR + j] = e;
       if (e) lastx = j * 64 + 63 - clz64(e);
       s.last[ly * T::WPR + j] = (u16)lastx;
     }
   }
   __syncthreads();
 
-  // 3. unite runs of rows ly-1, ly
+  // 3. unite runs of rows ly-1, ly (all row pairs at once)
   for (int c = tid; c < T::NCH; c += T::NT) {
     int ly = c / T::CPR, cc = c % T::CPR;
     if (ly == 0 || ly >= th || cc * 16 >= tw) continue;
