@@ -154,6 +154,71 @@ def run_gpu(work, steps: int, warmup: int):
                 emit_alg_bytes_per_launch=alg / len(gpu_imgs), counts=counts)
 
 
+def run_batch(n_images: int, steps: int, warmup: int):
+    """The uneven batch: one captured launch sequence per step (graph
+    replay), autotuned variant; then the same images one launch per image."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2006_09299_amd as ccl
+    from paper_2006_09299_amd import tune
+
+    dev = torch.device("cuda:0")
+    specs = synth.batch_specs(n_images)
+    imgs = []
+    for i, sp in enumerate(specs):
+        imgs.append(torch.from_numpy(sp.make()).to(dev))
+        if (i + 1) % 1024 == 0:
+            say(f"  generated {i + 1}/{n_images} batch images")
+    px = sum(sp.pixels for sp in specs)
+    sample = imgs[:: max(1, n_images // 256)]
+    variant = tune.autotune(sample)
+    say(f"  autotuned variant {variant} {ccl.variant_info(variant)} on {len(sample)} sampled images")
+    # capacities from one pass
+    rs = ccl.label_batch(imgs, variant=variant)
+    caps = [r.n_labels + 16 for r in rs]
+    del rs
+    plan = ccl.BatchPlan(imgs, variant=variant, caps=caps)
+    plan.capture()
+    for _ in range(warmup):
+        plan.replay()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    lat = []
+    a.record()
+    for _ in range(steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        plan.replay()
+        e1.record()
+        lat.append((e0, e1))
+    b.record()
+    torch.cuda.synchronize()
+    batch_ms = a.elapsed_time(b) / steps
+    lat_ms = sorted(x.elapsed_time(y) for x, y in lat)
+    # one launch per image (same variant, preallocated buffers per image)
+    bufs = [ccl.Buffers(int(t.shape[1]), int(t.shape[0]), c, dev, variant=variant) for t, c in zip(imgs, caps)]
+    for t, bf in zip(imgs, bufs):
+        ccl.launch(t, bf)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(steps):
+        for t, bf in zip(imgs, bufs):
+            ccl.launch(t, bf)
+    b.record()
+    torch.cuda.synchronize()
+    loop_ms = a.elapsed_time(b) / steps
+    out = {"images": n_images, "Gpixel": round(px / 1e9, 4), "variant": variant,
+           "tile": list(ccl.variant_info(variant)[:2]), "hash_reduce": ccl.variant_info(variant)[2],
+           "graph_ms_per_batch": round(batch_ms, 3), "Gpixel_s": round(px / (batch_ms / 1e3) / 1e9, 2),
+           "batch_latency_ms_p50": round(lat_ms[len(lat_ms) // 2], 3), "batch_latency_ms_max": round(lat_ms[-1], 3),
+           "per_image_loop_ms": round(loop_ms, 3),
+           "per_image_loop_Gpixel_s": round(px / (loop_ms / 1e3) / 1e9, 2),
+           "speedup_vs_loop": round(loop_ms / batch_ms, 2)}
+    say(f"  batch: {json.dumps(out)}")
+    return out
+
+
 def cpu_baseline(work, budget_s: float = 15.0):
     """The oracle as it stands, single-threaded, on a bounded sample."""
     import oracle
@@ -241,6 +306,9 @@ def main():
             "k_tile_emit_hbm_frac": round(r2["emit_alg_bytes_per_launch"] / (r2["emit_avg_ms"] / 1e3) / 1e9
                                           / HBM_PEAK_GBS, 4),
             "kernel_avg_ms": {k: round(v, 5) for k, v in r2["kernel_avg_ms"].items()}}}
+    if args.workload == "sweep8192" and not args.no_also:
+        say("bench: secondary workload batch4096")
+        out.setdefault("also", {})["batch4096"] = run_batch(4096, max(3, args.steps), 1)
     if not args.no_cpu_baseline:
         say("bench: cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(work)

@@ -101,21 +101,44 @@ int ccl_label_traced(const uint8_t *img, int32_t w, int32_t h, int64_t pitch, co
 /* [host] Name of kernel k (0..CCL_TRACE_EVENTS-2) in launch order, or NULL. */
 const char *ccl_kernel_name(int k);
 
-/* [host] Bytes of the descriptor block and of the workspace for a batch of
- * `n` images described in `imgs` [host]. */
-int ccl_batch_sizes(const ccl_image_t *imgs, int32_t n, size_t *desc_bytes, size_t *ws_bytes);
+/* Variants: the path compiled for several tile shapes and for two ways of
+ * summing the partial features of components that cross tiles (an LDS hash
+ * table per group of tiles, or direct global atomics).  All variants give
+ * identical results; they differ in speed per workload.  Variant 0 is the
+ * default of ccl_label. */
 
-/* [host] Write the batch's device descriptor block into `host_desc`
- * (desc_bytes from ccl_batch_sizes); the caller copies it to device memory
- * (`dev_desc`) before ccl_label_batch runs. */
-int ccl_batch_prepare(const ccl_image_t *imgs, int32_t n, void *host_desc, size_t desc_bytes);
+/* [host] Number of compiled variants. */
+int32_t ccl_num_variants(void);
 
-/* Label `n` images in one sequence of launches (each kernel covers every
- * tile of every image).  `dev_desc` holds the block written by
- * ccl_batch_prepare; `imgs` [host] is the same array.  Capturable in a
- * hipGraph: no allocation, no host synchronisation, no memset. */
-int ccl_label_batch(const ccl_image_t *imgs, int32_t n, const void *dev_desc, void *ws, size_t ws_bytes,
-                    void *stream);
+/* [host] Tile rows, tile columns and reduction (1 = LDS hash, 0 = direct
+ * atomics) of `variant`; CCL_EINVAL for an unknown index. */
+int ccl_variant_info(int32_t variant, int32_t *tile_h, int32_t *tile_w, int32_t *hash_reduce);
+
+/* [host] Workspace bytes of `variant` for a w x h image (pure; 0 on bad input). */
+size_t ccl_workspace_bytes_v(int32_t w, int32_t h, int32_t variant);
+
+/* ccl_label with an explicit variant. */
+int ccl_label_v(const uint8_t *img, int32_t w, int32_t h, int64_t pitch, const ccl_outputs_t *out, void *ws,
+                size_t ws_bytes, void *stream, int32_t variant);
+
+/* Batch: `n` images labeled by one sequence of launches in which every
+ * kernel covers every tile of every image (sizes may all differ).
+ *
+ * [host] ccl_batch_sizes: bytes of the device descriptor block and of the
+ * workspace for the images described in `imgs` [host] under `variant`. */
+int ccl_batch_sizes(const ccl_image_t *imgs, int32_t n, int32_t variant, size_t *desc_bytes, size_t *ws_bytes);
+
+/* [host] Write the descriptor block into `host_desc` (desc_bytes from
+ * ccl_batch_sizes); the caller copies it to device memory before
+ * ccl_label_batch runs and keeps it there while the batch may run again. */
+int ccl_batch_prepare(const ccl_image_t *imgs, int32_t n, int32_t variant, void *host_desc, size_t desc_bytes);
+
+/* Enqueue the batch.  `dev_desc` [device] holds the block written by
+ * ccl_batch_prepare for the same `imgs` [host] and `variant`.  Capturable in
+ * a hipGraph and replayable: it allocates nothing, never synchronises and
+ * records no memset (every kernel writes all the scratch it reads). */
+int ccl_label_batch(const ccl_image_t *imgs, int32_t n, int32_t variant, const void *dev_desc, void *ws,
+                    size_t ws_bytes, void *stream);
 
 /* [host] Static message for a CCL_E* code. */
 const char *ccl_strerror(int code);

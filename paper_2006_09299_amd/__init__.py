@@ -20,7 +20,7 @@ from typing import Optional
 import torch
 
 from . import _capi
-from ._capi import CclError, strerror, tile_shape, workspace_bytes  # noqa: F401
+from ._capi import CclError, num_variants, strerror, tile_shape, variant_info, workspace_bytes  # noqa: F401
 
 FEATURE_BYTES = 40  # ccl_feature_t: int32 xmin, xmax, ymin, ymax; int64 S, Sx, Sy
 
@@ -56,14 +56,15 @@ class Result:
 class Buffers:
     """Preallocated outputs + workspace for repeated calls on one image shape."""
 
-    def __init__(self, w: int, h: int, cap: int, device, labels: bool = True):
+    def __init__(self, w: int, h: int, cap: int, device, labels: bool = True, variant: int = 0):
         self.w, self.h, self.cap = int(w), int(h), int(cap)
+        self.variant = int(variant)
         self.labels = torch.empty((h, w), dtype=torch.int32, device=device) if labels else None
         self.features = torch.empty((cap, 5), dtype=torch.int64, device=device)
         self.parent = torch.empty(cap, dtype=torch.int32, device=device)
         self.color = torch.empty(cap, dtype=torch.uint8, device=device)
         self.counts = torch.zeros(2, dtype=torch.int64, device=device)
-        self.ws_bytes = workspace_bytes(w, h)
+        self.ws_bytes = workspace_bytes(w, h, variant)
         self.ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=device)
         self.out = _capi.ccl_outputs_t(
             self.labels.data_ptr() if labels else None, self.features.data_ptr(), self.parent.data_ptr(),
@@ -91,12 +92,12 @@ def launch(img: torch.Tensor, buf: Buffers, stream: Optional[int] = None) -> Non
         raise ValueError("buffers were made for another shape")
     if stream is None:
         stream = torch.cuda.current_stream(img.device).cuda_stream
-    rc = _capi.lib().ccl_label(img.data_ptr(), w, h, pitch, ctypes.byref(buf.out), buf.ws.data_ptr(),
-                               buf.ws_bytes, ctypes.c_void_p(stream))
+    rc = _capi.lib().ccl_label_v(img.data_ptr(), w, h, pitch, ctypes.byref(buf.out), buf.ws.data_ptr(),
+                                 buf.ws_bytes, ctypes.c_void_p(stream), buf.variant)
     _capi.check(rc, "ccl_label")
 
 
-def label(img: torch.Tensor, cap: Optional[int] = None, labels: bool = True) -> Result:
+def label(img: torch.Tensor, cap: Optional[int] = None, labels: bool = True, variant: int = 0) -> Result:
     """Label one image; synchronises to read the number of labels.
 
     cap: table capacity; by default a quarter of the pixels, grown and rerun
@@ -106,7 +107,7 @@ def label(img: torch.Tensor, cap: Optional[int] = None, labels: bool = True) -> 
     if cap is None:
         cap = min(full, max(1024, full // 4))
     while True:
-        buf = Buffers(w, h, cap, img.device, labels=labels)
+        buf = Buffers(w, h, cap, img.device, labels=labels, variant=variant)
         launch(img, buf)
         counts = buf.counts.cpu()
         n, euler = int(counts[0]), int(counts[1])
@@ -114,3 +115,6 @@ def label(img: torch.Tensor, cap: Optional[int] = None, labels: bool = True) -> 
             break
         cap = n
     return Result(buf.labels, buf.features[:n], buf.parent[:n], buf.color[:n], n, euler)
+
+
+from .batch import BatchPlan, label_batch  # noqa: E402,F401

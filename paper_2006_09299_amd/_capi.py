@@ -37,8 +37,9 @@ class ccl_image_t(ctypes.Structure):
 
 
 EXPORTS = (
-    "ccl_workspace_bytes", "ccl_label", "ccl_label_traced", "ccl_kernel_name", "ccl_batch_sizes",
-    "ccl_batch_prepare", "ccl_label_batch", "ccl_strerror", "ccl_tile_shape",
+    "ccl_workspace_bytes", "ccl_label", "ccl_label_traced", "ccl_kernel_name", "ccl_num_variants",
+    "ccl_variant_info", "ccl_workspace_bytes_v", "ccl_label_v", "ccl_batch_sizes", "ccl_batch_prepare",
+    "ccl_label_batch", "ccl_strerror", "ccl_tile_shape",
 )
 TRACE_EVENTS = 11
 
@@ -70,14 +71,26 @@ def lib():
                                        ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]
         L.ccl_kernel_name.restype = ctypes.c_char_p
         L.ccl_kernel_name.argtypes = [ctypes.c_int]
+        L.ccl_num_variants.restype = ctypes.c_int32
+        L.ccl_num_variants.argtypes = []
+        L.ccl_variant_info.restype = ctypes.c_int
+        L.ccl_variant_info.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32)]
+        L.ccl_workspace_bytes_v.restype = ctypes.c_size_t
+        L.ccl_workspace_bytes_v.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+        L.ccl_label_v.restype = ctypes.c_int
+        L.ccl_label_v.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+                                  ctypes.POINTER(ccl_outputs_t), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p,
+                                  ctypes.c_int32]
         L.ccl_batch_sizes.restype = ctypes.c_int
-        L.ccl_batch_sizes.argtypes = [ctypes.POINTER(ccl_image_t), ctypes.c_int32,
+        L.ccl_batch_sizes.argtypes = [ctypes.POINTER(ccl_image_t), ctypes.c_int32, ctypes.c_int32,
                                       ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]
         L.ccl_batch_prepare.restype = ctypes.c_int
-        L.ccl_batch_prepare.argtypes = [ctypes.POINTER(ccl_image_t), ctypes.c_int32, ctypes.c_void_p, ctypes.c_size_t]
+        L.ccl_batch_prepare.argtypes = [ctypes.POINTER(ccl_image_t), ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                        ctypes.c_size_t]
         L.ccl_label_batch.restype = ctypes.c_int
-        L.ccl_label_batch.argtypes = [ctypes.POINTER(ccl_image_t), ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
-                                      ctypes.c_size_t, ctypes.c_void_p]
+        L.ccl_label_batch.argtypes = [ctypes.POINTER(ccl_image_t), ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
         L.ccl_strerror.restype = ctypes.c_char_p
         L.ccl_strerror.argtypes = [ctypes.c_int]
         L.ccl_tile_shape.restype = None
@@ -95,8 +108,19 @@ def check(code: int, where: str) -> None:
         raise CclError(code, where)
 
 
-def workspace_bytes(w: int, h: int) -> int:
-    return int(lib().ccl_workspace_bytes(int(w), int(h)))
+def workspace_bytes(w: int, h: int, variant: int = 0) -> int:
+    return int(lib().ccl_workspace_bytes_v(int(w), int(h), int(variant)))
+
+
+def num_variants() -> int:
+    return int(lib().ccl_num_variants())
+
+
+def variant_info(v: int):
+    """(tile rows, tile columns, uses the LDS hash reduction)"""
+    th, tw, hs = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    check(lib().ccl_variant_info(int(v), ctypes.byref(th), ctypes.byref(tw), ctypes.byref(hs)), "ccl_variant_info")
+    return th.value, tw.value, bool(hs.value)
 
 
 def kernel_names():

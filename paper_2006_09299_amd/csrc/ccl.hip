@@ -1,5 +1,9 @@
 // ccl.hip -- C-ABI of libccl.so: argument checks, workspace layout and the
 // launch sequence of ccl_pipeline.h on a HIP stream (gfx950).
+//
+// Variants: the same path compiled for several tile shapes and for the two
+// root-reduction schemes (LDS hash per tile group / direct atomics).  The
+// batch entry points and the tuner pick one by index; ccl_label uses 0.
 #include <hip/hip_runtime.h>
 
 #include <string.h>
@@ -9,9 +13,29 @@
 
 namespace {
 
-using T = ccl::Tile<32, 128>;
-
 static_assert(sizeof(ccl::Feature) == sizeof(ccl_feature_t), "feature record layout");
+
+template <int TH, int TW, bool HASH>
+struct V {
+  using T = ccl::Tile<TH, TW>;
+  static constexpr bool hash = HASH;
+};
+
+// variant index -> (tile rows, tile columns, reduction)
+constexpr int NVARIANTS = 6;
+
+template <class F>
+int with_variant(int v, F&& f) {
+  switch (v) {
+    case 0: return f(V<32, 128, true>{});
+    case 1: return f(V<32, 128, false>{});
+    case 2: return f(V<16, 128, true>{});
+    case 3: return f(V<32, 256, true>{});
+    case 4: return f(V<64, 128, true>{});
+    case 5: return f(V<16, 256, true>{});
+    default: return CCL_EINVAL;
+  }
+}
 
 struct HipLauncher {
   hipStream_t stream;
@@ -59,44 +83,87 @@ ccl::ImgDesc to_desc(const uint8_t* img, int32_t w, int32_t h, int64_t pitch, co
 
 struct Totals {
   int64_t tiles = 0, nodes = 0, cells = 0, blocks = 0, items = 0;
+  bool too_big() const { return nodes >= INT32_MAX || tiles >= INT32_MAX || blocks >= INT32_MAX; }
 };
+
+// geometry of a batch under variant Vt; fills ds (may be null)
+template <class Vt>
+int place_batch(const ccl_image_t* imgs, int32_t n, ccl::ImgDesc* ds, Totals& t) {
+  for (int32_t i = 0; i < n; i++) {
+    const ccl_image_t& im = imgs[i];
+    if (!image_args_ok(im.img, im.w, im.h, im.pitch, &im.out)) return CCL_EINVAL;
+    ccl::ImgDesc d = to_desc(im.img, im.w, im.h, im.pitch, &im.out);
+    ccl::place_image<typename Vt::T>(d, t.tiles, t.nodes, t.cells, t.blocks, t.items);
+    if (ds) ds[i] = d;
+  }
+  return t.too_big() ? CCL_ETOOBIG : CCL_OK;
+}
+
+int label_one(const uint8_t* img, int32_t w, int32_t h, int64_t pitch, const ccl_outputs_t* out, void* ws,
+              size_t ws_bytes, void* stream, void* const* events, int32_t variant) {
+  if (!image_args_ok(img, w, h, pitch, out) || !ws) return CCL_EINVAL;
+  return with_variant(variant, [&](auto vt) -> int {
+    using Vt = decltype(vt);
+    using T = typename Vt::T;
+    ccl::ImgDesc d = to_desc(img, w, h, pitch, out);
+    Totals t;
+    ccl::place_image<T>(d, t.tiles, t.nodes, t.cells, t.blocks, t.items);
+    if (t.too_big()) return CCL_ETOOBIG;
+    ccl::Layout L = ccl::make_layout<T>(t.tiles, t.nodes, t.cells, t.blocks);
+    if (ws_bytes < L.bytes) return CCL_ENOSPC;
+    ccl::Work wk = ccl::make_work(L, ws);
+    HipLauncher hl{static_cast<hipStream_t>(stream)};
+    hl.events = events;
+    ccl::OneImage src{d};
+    ccl::enqueue<T, Vt::hash>(hl, src, wk, t.tiles, t.items, t.blocks, 1);
+    hl.finish();
+    return hl.err == hipSuccess ? CCL_OK : CCL_EHIP;
+  });
+}
 
 }  // namespace
 
 extern "C" {
 
-size_t ccl_workspace_bytes(int32_t w, int32_t h) {
-  if (w <= 0 || h <= 0) return 0;
-  ccl::ImgDesc d;
-  memset(&d, 0, sizeof(d));
-  d.w = w;
-  d.h = h;
-  Totals t;
-  ccl::place_image<T>(d, t.tiles, t.nodes, t.cells, t.blocks, t.items);
-  return ccl::make_layout<T>(t.tiles, t.nodes, t.cells, t.blocks).bytes;
+int32_t ccl_num_variants(void) { return NVARIANTS; }
+
+int ccl_variant_info(int32_t variant, int32_t* tile_h, int32_t* tile_w, int32_t* hash_reduce) {
+  return with_variant(variant, [&](auto vt) -> int {
+    using Vt = decltype(vt);
+    if (tile_h) *tile_h = Vt::T::TH;
+    if (tile_w) *tile_w = Vt::T::TW;
+    if (hash_reduce) *hash_reduce = Vt::hash ? 1 : 0;
+    return CCL_OK;
+  });
 }
 
-static int label_one(const uint8_t* img, int32_t w, int32_t h, int64_t pitch, const ccl_outputs_t* out, void* ws,
-                     size_t ws_bytes, void* stream, void* const* events) {
-  if (!image_args_ok(img, w, h, pitch, out) || !ws) return CCL_EINVAL;
-  ccl::ImgDesc d = to_desc(img, w, h, pitch, out);
-  Totals t;
-  ccl::place_image<T>(d, t.tiles, t.nodes, t.cells, t.blocks, t.items);
-  if (t.nodes >= INT32_MAX) return CCL_ETOOBIG;
-  ccl::Layout L = ccl::make_layout<T>(t.tiles, t.nodes, t.cells, t.blocks);
-  if (ws_bytes < L.bytes) return CCL_ENOSPC;
-  ccl::Work wk = ccl::make_work(L, ws);
-  HipLauncher hl{static_cast<hipStream_t>(stream)};
-  hl.events = events;
-  ccl::OneImage src{d};
-  ccl::enqueue<T>(hl, src, wk, t.tiles, t.items, t.blocks, 1);
-  hl.finish();
-  return hl.err == hipSuccess ? CCL_OK : CCL_EHIP;
+size_t ccl_workspace_bytes_v(int32_t w, int32_t h, int32_t variant) {
+  if (w <= 0 || h <= 0) return 0;
+  size_t bytes = 0;
+  with_variant(variant, [&](auto vt) -> int {
+    using T = typename decltype(vt)::T;
+    ccl::ImgDesc d;
+    memset(&d, 0, sizeof(d));
+    d.w = w;
+    d.h = h;
+    Totals t;
+    ccl::place_image<T>(d, t.tiles, t.nodes, t.cells, t.blocks, t.items);
+    bytes = ccl::make_layout<T>(t.tiles, t.nodes, t.cells, t.blocks).bytes;
+    return CCL_OK;
+  });
+  return bytes;
 }
+
+size_t ccl_workspace_bytes(int32_t w, int32_t h) { return ccl_workspace_bytes_v(w, h, 0); }
 
 int ccl_label(const uint8_t* img, int32_t w, int32_t h, int64_t pitch, const ccl_outputs_t* out, void* ws,
               size_t ws_bytes, void* stream) {
-  return label_one(img, w, h, pitch, out, ws, ws_bytes, stream, nullptr);
+  return label_one(img, w, h, pitch, out, ws, ws_bytes, stream, nullptr, 0);
+}
+
+int ccl_label_v(const uint8_t* img, int32_t w, int32_t h, int64_t pitch, const ccl_outputs_t* out, void* ws,
+                size_t ws_bytes, void* stream, int32_t variant) {
+  return label_one(img, w, h, pitch, out, ws, ws_bytes, stream, nullptr, variant);
 }
 
 int ccl_label_traced(const uint8_t* img, int32_t w, int32_t h, int64_t pitch, const ccl_outputs_t* out, void* ws,
@@ -104,7 +171,7 @@ int ccl_label_traced(const uint8_t* img, int32_t w, int32_t h, int64_t pitch, co
   if (!events) return CCL_EINVAL;
   for (int i = 0; i < CCL_TRACE_EVENTS; i++)
     if (!events[i]) return CCL_EINVAL;
-  return label_one(img, w, h, pitch, out, ws, ws_bytes, stream, events);
+  return label_one(img, w, h, pitch, out, ws, ws_bytes, stream, events, 0);
 }
 
 const char* ccl_kernel_name(int k) {
@@ -114,53 +181,44 @@ const char* ccl_kernel_name(int k) {
   return k >= 0 && k < CCL_TRACE_EVENTS - 1 ? names[k] : nullptr;
 }
 
-int ccl_batch_sizes(const ccl_image_t* imgs, int32_t n, size_t* desc_bytes, size_t* ws_bytes) {
+int ccl_batch_sizes(const ccl_image_t* imgs, int32_t n, int32_t variant, size_t* desc_bytes, size_t* ws_bytes) {
   if (!imgs || n <= 0 || !desc_bytes || !ws_bytes) return CCL_EINVAL;
-  Totals t;
-  for (int32_t i = 0; i < n; i++) {
-    const ccl_image_t& im = imgs[i];
-    if (!image_args_ok(im.img, im.w, im.h, im.pitch, &im.out)) return CCL_EINVAL;
-    ccl::ImgDesc d = to_desc(im.img, im.w, im.h, im.pitch, &im.out);
-    ccl::place_image<T>(d, t.tiles, t.nodes, t.cells, t.blocks, t.items);
-  }
-  if (t.nodes >= INT32_MAX || t.tiles >= INT32_MAX || t.blocks >= INT32_MAX) return CCL_ETOOBIG;
-  *desc_bytes = sizeof(ccl::ImgDesc) * (size_t)n;
-  *ws_bytes = ccl::make_layout<T>(t.tiles, t.nodes, t.cells, t.blocks).bytes;
-  return CCL_OK;
+  return with_variant(variant, [&](auto vt) -> int {
+    using Vt = decltype(vt);
+    Totals t;
+    int rc = place_batch<Vt>(imgs, n, nullptr, t);
+    if (rc != CCL_OK) return rc;
+    *desc_bytes = sizeof(ccl::ImgDesc) * (size_t)n;
+    *ws_bytes = ccl::make_layout<typename Vt::T>(t.tiles, t.nodes, t.cells, t.blocks).bytes;
+    return CCL_OK;
+  });
 }
 
-int ccl_batch_prepare(const ccl_image_t* imgs, int32_t n, void* host_desc, size_t desc_bytes) {
+int ccl_batch_prepare(const ccl_image_t* imgs, int32_t n, int32_t variant, void* host_desc, size_t desc_bytes) {
   if (!imgs || n <= 0 || !host_desc || desc_bytes < sizeof(ccl::ImgDesc) * (size_t)n) return CCL_EINVAL;
-  ccl::ImgDesc* ds = static_cast<ccl::ImgDesc*>(host_desc);
-  Totals t;
-  for (int32_t i = 0; i < n; i++) {
-    const ccl_image_t& im = imgs[i];
-    if (!image_args_ok(im.img, im.w, im.h, im.pitch, &im.out)) return CCL_EINVAL;
-    ds[i] = to_desc(im.img, im.w, im.h, im.pitch, &im.out);
-    ccl::place_image<T>(ds[i], t.tiles, t.nodes, t.cells, t.blocks, t.items);
-  }
-  if (t.nodes >= INT32_MAX || t.tiles >= INT32_MAX || t.blocks >= INT32_MAX) return CCL_ETOOBIG;
-  return CCL_OK;
+  return with_variant(variant, [&](auto vt) -> int {
+    Totals t;
+    return place_batch<decltype(vt)>(imgs, n, static_cast<ccl::ImgDesc*>(host_desc), t);
+  });
 }
 
-int ccl_label_batch(const ccl_image_t* imgs, int32_t n, const void* dev_desc, void* ws, size_t ws_bytes,
-                    void* stream) {
+int ccl_label_batch(const ccl_image_t* imgs, int32_t n, int32_t variant, const void* dev_desc, void* ws,
+                    size_t ws_bytes, void* stream) {
   if (!imgs || n <= 0 || !dev_desc || !ws) return CCL_EINVAL;
-  Totals t;
-  for (int32_t i = 0; i < n; i++) {
-    const ccl_image_t& im = imgs[i];
-    if (!image_args_ok(im.img, im.w, im.h, im.pitch, &im.out)) return CCL_EINVAL;
-    ccl::ImgDesc d = to_desc(im.img, im.w, im.h, im.pitch, &im.out);
-    ccl::place_image<T>(d, t.tiles, t.nodes, t.cells, t.blocks, t.items);
-  }
-  if (t.nodes >= INT32_MAX || t.tiles >= INT32_MAX || t.blocks >= INT32_MAX) return CCL_ETOOBIG;
-  ccl::Layout L = ccl::make_layout<T>(t.tiles, t.nodes, t.cells, t.blocks);
-  if (ws_bytes < L.bytes) return CCL_ENOSPC;
-  ccl::Work wk = ccl::make_work(L, ws);
-  HipLauncher hl{static_cast<hipStream_t>(stream)};
-  ccl::ManyImages src{static_cast<const ccl::ImgDesc*>(dev_desc), n};
-  ccl::enqueue<T>(hl, src, wk, t.tiles, t.items, t.blocks, n);
-  return hl.err == hipSuccess ? CCL_OK : CCL_EHIP;
+  return with_variant(variant, [&](auto vt) -> int {
+    using Vt = decltype(vt);
+    using T = typename Vt::T;
+    Totals t;
+    int rc = place_batch<Vt>(imgs, n, nullptr, t);
+    if (rc != CCL_OK) return rc;
+    ccl::Layout L = ccl::make_layout<T>(t.tiles, t.nodes, t.cells, t.blocks);
+    if (ws_bytes < L.bytes) return CCL_ENOSPC;
+    ccl::Work wk = ccl::make_work(L, ws);
+    HipLauncher hl{static_cast<hipStream_t>(stream)};
+    ccl::ManyImages src{static_cast<const ccl::ImgDesc*>(dev_desc), n};
+    ccl::enqueue<T, Vt::hash>(hl, src, wk, t.tiles, t.items, t.blocks, n);
+    return hl.err == hipSuccess ? CCL_OK : CCL_EHIP;
+  });
 }
 
 const char* ccl_strerror(int code) {
@@ -175,9 +233,6 @@ const char* ccl_strerror(int code) {
   }
 }
 
-void ccl_tile_shape(int32_t* tile_h, int32_t* tile_w) {
-  if (tile_h) *tile_h = T::TH;
-  if (tile_w) *tile_w = T::TW;
-}
+void ccl_tile_shape(int32_t* tile_h, int32_t* tile_w) { ccl_variant_info(0, tile_h, tile_w, nullptr); }
 
 }  // extern "C"

@@ -30,7 +30,8 @@
 //                   atomicMin union-find in HBM.
 //   k_flatten     : final root of every border node (full path compression).
 //   k_reduce_roots: the root takes the minimum raster key and the sum of the
-//                   partial features (LDS hash per group of tiles first).
+//                   partial features (LDS hash per group of tiles first;
+//                   k_reduce_direct is the variant with direct atomics).
 //   k_leaders     : which border node holds its component's first pixel; rank
 //                   of that pixel among the components starting in the same
 //                   row of the same tile.
@@ -913,6 +914,32 @@ __global__ void __launch_bounds__(RH_T) k_reduce_roots(Src src, Work wk, int64_t
   }
 }
 
+// The same reduction without the LDS table: every non-root node adds its
+// partial directly into its root with global atomics (one wave per tile).
+// Cheaper when components rarely span tiles; contended on giant ones.
+template <class T, class Src>
+__global__ void __launch_bounds__(64) k_reduce_direct(Src src, Work wk) {
+  const int64_t gt = blockIdx.x;
+  const ImgDesc& d = src.by_tile(gt);
+  const int64_t nbase = tile_node_base<T>(d, gt - d.tile0);
+  const int nb = wk.nbt[gt];
+  for (int i = threadIdx.x; i < nb; i += 64) {
+    int node = (int)(nbase + i);
+    int r = wk.gpar[node];
+    if (r == node) continue;
+    atomicMin(&wk.gminkey[r], wk.gkey[node]);
+    Feature f = wk.gacc[node];
+    Feature* g = &wk.gacc[r];
+    atomicMin(&g->xmin, f.xmin);
+    atomicMax(&g->xmax, f.xmax);
+    atomicMin(&g->ymin, f.ymin);
+    atomicMax(&g->ymax, f.ymax);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&g->S), (unsigned long long)f.S);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&g->Sx), (unsigned long long)f.Sx);
+    atomicAdd(reinterpret_cast<unsigned long long*>(&g->Sy), (unsigned long long)f.Sy);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // K4: leaders (node holding the component's first pixel) and their ranks
 
@@ -1344,13 +1371,16 @@ inline void place_image(ImgDesc& d, int64_t& tiles, int64_t& nodes, int64_t& cel
 
 // Enqueue the whole path.  `L` provides launch(kernel, grid, block, args...)
 // in stream order.  Every image's derived fields must come from place_image.
-template <class T, class Src, class Launcher>
+// HASH selects the root reduction: LDS hash per group of tiles, or direct
+// global atomics per node.
+template <class T, bool HASH, class Src, class Launcher>
 inline void enqueue(Launcher& L, const Src& src, const Work& wk, int64_t tiles, int64_t items, int64_t blocks,
                     int64_t nimages) {
   L.launch(k_tile_export<T, Src>, tiles, T::NT, src, wk);
   if (items > 0) L.launch(k_border_merge<T, Src>, (items + 255) / 256, 256, src, wk, items);
   L.launch(k_flatten<T, Src>, tiles, 64, src, wk);
-  L.launch(k_reduce_roots<T, Src>, (tiles + RH_TILES - 1) / RH_TILES, RH_T, src, wk, tiles);
+  if (HASH) L.launch(k_reduce_roots<T, Src>, (tiles + RH_TILES - 1) / RH_TILES, RH_T, src, wk, tiles);
+  else L.launch(k_reduce_direct<T, Src>, tiles, 64, src, wk);
   L.launch(k_leaders<T, Src>, tiles, 64, src, wk);
   L.launch(k_scan_reduce<Src>, blocks, SCAN_T, src, wk);
   L.launch(k_scan_blocks<Src>, nimages, SCAN_T, src, wk);

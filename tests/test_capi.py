@@ -70,11 +70,29 @@ def test_batch_sizes_and_prepare_on_host():
     for i, (w, h) in enumerate([(64, 64), (100, 33), (1, 1)]):
         imgs[i] = _capi.ccl_image_t(fake, w, h, w, _capi.ccl_outputs_t(fake, fake, fake, fake, 8, fake))
     db, wb = ctypes.c_size_t(), ctypes.c_size_t()
-    assert _capi.lib().ccl_batch_sizes(imgs, 3, ctypes.byref(db), ctypes.byref(wb)) == 0
-    assert db.value > 0 and wb.value >= _capi.workspace_bytes(64, 64)
-    host = (ctypes.c_char * db.value)()
-    assert _capi.lib().ccl_batch_prepare(imgs, 3, host, db.value) == 0
-    assert _capi.lib().ccl_batch_prepare(imgs, 3, host, db.value - 1) == _capi.CCL_EINVAL
+    L = _capi.lib()
+    for v in range(_capi.num_variants()):
+        assert L.ccl_batch_sizes(imgs, 3, v, ctypes.byref(db), ctypes.byref(wb)) == 0
+        assert db.value > 0 and wb.value >= _capi.workspace_bytes(64, 64, v)
+        host = (ctypes.c_char * db.value)()
+        assert L.ccl_batch_prepare(imgs, 3, v, host, db.value) == 0
+        assert L.ccl_batch_prepare(imgs, 3, v, host, db.value - 1) == _capi.CCL_EINVAL
+    assert L.ccl_batch_sizes(imgs, 3, _capi.num_variants(), ctypes.byref(db), ctypes.byref(wb)) == _capi.CCL_EINVAL
     imgs[1].pitch = 10  # < w
-    assert _capi.lib().ccl_batch_sizes(imgs, 3, ctypes.byref(db), ctypes.byref(wb)) == _capi.CCL_EINVAL
-    assert _capi.lib().ccl_label_batch(imgs, 0, host, host, 1, None) == _capi.CCL_EINVAL
+    assert L.ccl_batch_sizes(imgs, 3, 0, ctypes.byref(db), ctypes.byref(wb)) == _capi.CCL_EINVAL
+    assert L.ccl_label_batch(imgs, 0, 0, host, host, 1, None) == _capi.CCL_EINVAL
+
+
+def test_variants_are_described():
+    n = _capi.num_variants()
+    assert n >= 2
+    seen = set()
+    for v in range(n):
+        th, tw, hs = _capi.variant_info(v)
+        assert th >= 1 and tw % 64 == 0
+        seen.add((th, tw, hs))
+        assert _capi.workspace_bytes(1000, 700, v) > 0
+    assert len(seen) == n
+    assert _capi.variant_info(0)[:2] == _capi.tile_shape()
+    with pytest.raises(_capi.CclError):
+        _capi.variant_info(n)
