@@ -219,6 +219,49 @@ def run_batch(n_images: int, steps: int, warmup: int):
     return out
 
 
+def run_serve(n_requests: int, rate_hz: float = 2000.0, warmup_s: float = 1.0, pool_images: int = 128,
+              budget_gib: int = 48, batched: bool = True):
+    """Open-loop Poisson request stream through the serving loop.  Requests
+    draw their image from a pool of pre-generated host images with the
+    stream's size / density distribution (sides log-uniform in [256, 8192]).
+    Latency = completion observed - scheduled arrival."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2006_09299_amd.serve import Server
+
+    warm = int(warmup_s * rate_hz)
+    stream = synth.serve_stream(n_requests + warm, rate_hz=rate_hz)
+    host = []
+    for i in range(pool_images):
+        host.append(torch.from_numpy(stream[i].spec.make()).pin_memory())
+    say(f"  serve: {pool_images} pooled images, mean {np.mean([t.numel() for t in host]) / 1e6:.2f} Mpx")
+    srv = Server(budget_gib << 30, max_slots=512 if batched else 1, streams=4 if batched else 1,
+                 max_batch=64 if batched else 1)
+    lat, px_done, t_first, t_last, qmax = [], 0, None, None, 0
+    i = 0
+    start = srv.now()
+    while i < len(stream) or not srv.idle():
+        now = srv.now() - start
+        while i < len(stream) and stream[i].arrival_s <= now:
+            srv.submit(i, host[i % pool_images], arrival=start + stream[i].arrival_s)
+            i += 1
+        qmax = max(qmax, len(srv.queue))
+        for r in srv.step():
+            if r.rid >= warm:
+                lat.append(r.done - r.arrival)
+                px_done += r.img.numel()
+                t_first = r.arrival if t_first is None else min(t_first, r.arrival)
+                t_last = r.done if t_last is None else max(t_last, r.done)
+            srv.release(r.rid)
+    lat.sort()
+    q = lambda f: round(1e3 * lat[min(len(lat) - 1, int(f * len(lat)))], 3)
+    span = t_last - t_first
+    return {"requests": len(lat), "rate_hz": rate_hz, "offered_Gpixel_s": round(px_done / (len(lat) / rate_hz) / 1e9, 2),
+            "Gpixel_s": round(px_done / span / 1e9, 2), "p50_ms": q(0.50), "p99_ms": q(0.99), "max_ms": round(1e3 * lat[-1], 3),
+            "max_queue": qmax, "rejected": srv.rejected, "streams": len(srv.streams), "max_batch": srv.max_batch}
+
+
 def cpu_baseline(work, budget_s: float = 15.0):
     """The oracle as it stands, single-threaded, on a bounded sample."""
     import oracle
@@ -249,6 +292,7 @@ def main():
     ap.add_argument("--workload", default="sweep8192", choices=["sweep8192", "structured16384"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-also", action="store_true", help="skip the secondary structured16384 measurement")
+    ap.add_argument("--serve-requests", type=int, default=20000, help="measured requests of the serving leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run one plain device-to-device copy of MIB MiB (scales the HBM byte counters)")
     args = ap.parse_args()
@@ -309,6 +353,13 @@ def main():
     if args.workload == "sweep8192" and not args.no_also:
         say("bench: secondary workload batch4096")
         out.setdefault("also", {})["batch4096"] = run_batch(4096, max(3, args.steps), 1)
+    if args.workload == "sweep8192" and not args.no_also:
+        say("bench: serving (continuous batching), then one request per launch")
+        sv = run_serve(args.serve_requests)
+        say(f"  serve: {json.dumps(sv)}")
+        sv1 = run_serve(args.serve_requests, batched=False)
+        say(f"  serve, one request per launch: {json.dumps(sv1)}")
+        out.setdefault("also", {})["serve"] = {"continuous_batching": sv, "one_request_per_launch": sv1}
     if not args.no_cpu_baseline:
         say("bench: cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(work)
