@@ -357,7 +357,7 @@ def main():
         say("bench: serving (continuous batching), then one request per launch")
         sv = run_serve(args.serve_requests)
         say(f"  serve: {json.dumps(sv)}")
-        sv1 = run_serve(args.serve_requests, batched=False)
+        sv1 = run_serve(min(args.serve_requests, 4000), batched=False)
         say(f"  serve, one request per launch: {json.dumps(sv1)}")
         out.setdefault("also", {})["serve"] = {"continuous_batching": sv, "one_request_per_launch": sv1}
     if not args.no_cpu_baseline:
