@@ -280,6 +280,7 @@ struct TileSmem {
   u16 ipre[T::NW];   // interior roots before word
   int nb, nint;
   int euler;
+  int uniform;       // 0: general tile; 1 + colour: every valid pixel has one colour
 };
 
 template <class T>
@@ -305,10 +306,11 @@ __device__ inline int iord_of(const TileSmem<T>& s, int r) {  // r: interior roo
 // Ends with a barrier; afterwards par[p] is the root position of every run
 // start p, bflag/rootm/bpre/ipre/nb/nint are valid.
 template <class T>
-__device__ void tile_label(TileSmem<T>& s, const u8* img, int64_t pitch, int x0, int y0, int tw, int th,
-                           bool vec_in) {
+__device__ int tile_label(TileSmem<T>& s, const u8* img, int64_t pitch, int x0, int y0, int tw, int th,
+                          bool vec_in) {
   const int tid = threadIdx.x;
-  // 1. load bytes, 16 pixels per chunk -> 16 bits
+  // 1. load bytes, 16 pixels per chunk -> 16 bits; vote on a one-colour tile
+  bool all0 = true, all1 = true;
   for (int c = tid; c < T::NCH; c += T::NT) {
     int ly = c / T::CPR, cx = (c % T::CPR) * 16;
     u32 m = 0;
@@ -323,9 +325,26 @@ __device__ void tile_label(TileSmem<T>& s, const u8* img, int64_t pitch, int x0,
       }
     }
     reinterpret_cast<u16*>(s.bits)[c] = (u16)m;
+    if (ly < th && cx < tw) {
+      u32 vm = (u32)valid_mask(0, tw - cx) & 0xFFFFu;
+      all0 = all0 && (m & vm) == 0;
+      all1 = all1 && (m & vm) == vm;
+    }
   }
   for (int i = tid; i < T::NW; i += T::NT) s.bflag[i] = 0;
-  __syncthreads();
+  const int u0 = __syncthreads_and(all0);
+  const int u1 = __syncthreads_and(all1);
+  if (u0 || u1) {
+    // one component covering the tile: its first pixel (0, 0) is the only
+    // run start that matters; callers take their one-colour path
+    if (tid == 0) {
+      s.uniform = u1 ? 2 : 1;
+      s.nb = 1;
+      s.nint = 0;
+    }
+    __syncthreads();
+    return u1 ? 2 : 1;
+  }
 
   // 2. run starts, 16 pixels per chunk; par[p] = p at every run start (the
   // only entries ever read); last start per word, one row per thread
@@ -470,9 +489,11 @@ __device__ void tile_label(TileSmem<T>& s, const u8* img, int64_t pitch, int x0,
     if (tid == 0) {
       s.nb = (int)cb;
       s.nint = (int)ci;
+      s.uniform = 0;
     }
   }
   __syncthreads();
+  return 0;
 }
 
 // Segments of one 16-pixel chunk: calls f(run_start_x, seg_begin, seg_end).
@@ -587,9 +608,49 @@ __global__ void __launch_bounds__(256) k_tile_export(Src src, Work wk) {
     if (d.counts) d.counts[1] = 0;
   }
 
-  tile_label<T>(s, d.img, d.pitch, x0, y0, tw, th, (d.flags & DF_VEC_IN) != 0);
-
+  const int uni = tile_label<T>(s, d.img, d.pitch, x0, y0, tw, th, (d.flags & DF_VEC_IN) != 0);
   const int64_t nbase = tile_node_base<T>(d, lt);
+
+  if (uni) {
+    // one-colour tile: a single border node whose first pixel is (x0, y0),
+    // features in closed form, every border pixel maps to node slot 0
+    const int col = uni - 1;
+    if (tid == 0) {
+      int32_t key = (int32_t)((int64_t)y0 * d.w + x0);
+      wk.gpar[nbase] = (int32_t)nbase;
+      wk.gkey[nbase] = key;
+      wk.gminkey[nbase] = key;
+      wk.grank[nbase] = 0;
+      Feature f;
+      f.xmin = x0; f.xmax = x0 + tw - 1; f.ymin = y0; f.ymax = y0 + th - 1;
+      f.S = (int64_t)tw * th;
+      f.Sx = (int64_t)th * ((int64_t)x0 * tw + (int64_t)tw * (tw - 1) / 2);
+      f.Sy = (int64_t)tw * ((int64_t)y0 * th + (int64_t)th * (th - 1) / 2);
+      wk.gacc[nbase] = f;
+      wk.nbt[gt] = 1;
+    }
+    for (int ly = tid; ly < th; ly += T::NT) wk.cgrid[d.c0 + (int64_t)(y0 + ly) * d.ntx + tx] = 0;
+    for (int t = tid; t < 2 * T::TW + 2 * T::TH; t += T::NT) {
+      if (t < 2 * T::TW) {
+        int x = t % T::TW;
+        (t >= T::TW ? wk.bidx_bot : wk.bidx_top)[gt * T::TW + x] = x < tw ? (u16)0 : (u16)0xFFFFu;
+      } else {
+        int k = t - 2 * T::TW;
+        int ly = k % T::TH;
+        (k >= T::TH ? wk.bidx_right : wk.bidx_left)[gt * T::TH + ly] = ly < th ? (u16)0 : (u16)0xFFFFu;
+      }
+    }
+    for (int t = tid; t < 2 * T::WPR + 2; t += T::NT) {
+      if (t < 2 * T::WPR) {
+        int j = t % T::WPR;
+        (t >= T::WPR ? wk.bits_bot : wk.bits_top)[gt * T::WPR + j] = col ? valid_mask(j, tw) : 0ull;
+      } else {
+        wk.bits_lr[gt * 2 + (t - 2 * T::WPR)] = col ? low_mask(th) : 0ull;
+      }
+    }
+    return;
+  }
+
   // 8. border node records, interior counts per row, accumulator init
   for (int wd = tid; wd < T::NW; wd += T::NT) {
     int ly = wd / T::WPR, j = wd % T::WPR;
@@ -1117,9 +1178,42 @@ __global__ void __launch_bounds__(256) k_tile_emit(Src src, Work wk) {
   const int th = d.h - y0 < T::TH ? d.h - y0 : T::TH;
   const int tid = threadIdx.x;
 
-  tile_label<T>(s, d.img, d.pitch, x0, y0, tw, th, (d.flags & DF_VEC_IN) != 0);
-
+  const int uni = tile_label<T>(s, d.img, d.pitch, x0, y0, tw, th, (d.flags & DF_VEC_IN) != 0);
   const int64_t nbase = tile_node_base<T>(d, lt);
+
+  if (uni) {
+    // one-colour tile: its single component is border node slot 0
+    const int col = uni - 1;
+    const int node = (int)nbase;
+    const int32_t canon = wk.rcanon[wk.gpar[node]];
+    if (tid == 0 && (wk.grank[node] & (int)HI)) {  // the component starts here
+      if (canon < d.cap) {
+        if (d.color) d.color[canon] = (u8)col;
+        if (d.parent)
+          d.parent[canon] = tx > 0 ? wk.rcanon[wk.gpar[col_node<T>(wk, d, tx - 1, y0, true)]] : 0;
+      }
+      if (d.counts)
+        atomicAdd(reinterpret_cast<unsigned long long*>(&d.counts[1]), (unsigned long long)(int64_t)(col ? 1 : -1));
+    }
+    if (d.labels) {
+      const bool vec = (d.flags & DF_VEC_LAB) != 0;
+      for (int q = tid; q < T::TH * (T::TW / 4); q += T::NT) {
+        int ly = q / (T::TW / 4), x = (q % (T::TW / 4)) * 4;
+        if (ly >= th || x >= tw) continue;
+        int32_t* dst = d.labels + (int64_t)(y0 + ly) * d.w + x0 + x;
+        if (vec && x + 4 <= tw) {
+          int4 v4;
+          v4.x = canon; v4.y = canon; v4.z = canon; v4.w = canon;
+          *reinterpret_cast<int4*>(dst) = v4;
+        } else {
+          int n = tw - x < 4 ? tw - x : 4;
+          for (int k = 0; k < n; k++) dst[k] = canon;
+        }
+      }
+    }
+    return;
+  }
+
   if (tid == 0) s.euler = 0;
   // 8. canonical ids of border roots; leader mask (interior roots lead)
   for (int wd = tid; wd < T::NW; wd += T::NT) s.lmask[wd] = s.rootm[wd] & ~s.bflag[wd];

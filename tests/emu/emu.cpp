@@ -163,6 +163,20 @@ emu_dim emu_block_idx() { return S.bidx; }
 emu_dim emu_block_dim() { return S.bdim; }
 emu_dim emu_grid_dim() { return S.gdim; }
 void emu_block_barrier() { wait_on(0); }
+int emu_block_vote_and(int pred) {
+  // count the live threads voting false; two barriers keep rounds apart
+  static int falses = 0;
+  static int phase = 0;
+  (void)phase;
+  emu_block_barrier();
+  if (S.f[S.cur].tid == 0) falses = 0;
+  emu_block_barrier();
+  if (!pred) falses++;
+  emu_block_barrier();
+  int r = falses == 0;
+  emu_block_barrier();
+  return r;
+}
 void emu_wave_exchange(unsigned long long v, unsigned long long* all64) {
   unsigned tid = S.f[S.cur].tid;
   unsigned wave = tid / 64;

@@ -46,6 +46,8 @@ void emu_wave_exchange(unsigned long long v, unsigned long long* all64);
 #define gridDim (emu_grid_dim())
 
 inline void __syncthreads() { emu_block_barrier(); }
+int emu_block_vote_and(int pred);
+inline int __syncthreads_and(int pred) { return emu_block_vote_and(pred); }
 
 template <class V>
 inline V __shfl_up(V v, unsigned d, int = 64) {
