@@ -108,6 +108,11 @@ struct Work {
   u64* bits_lr;      // [tiles*2] left column (bit = row), right column
   int32_t* cgrid;    // [sum h*ntx] per (row, tile column): starts, then base ids
   int32_t* bsum;     // [scan blocks]
+  // tile state handed from K1 to K6, tile raster order inside each tile
+  int32_t* tinfo;    // [tiles] general tile: runs << 2; one-colour tile: 1 + colour
+  u64* tstate;       // [tiles*3*NW] foreground bits, root masks, border-root masks
+  u16* tord;         // [tiles*N] root ordinal of every run, by run rank
+                     // (border roots first, then interior roots, raster order)
 };
 
 constexpr u32 HI = 0x80000000u;
@@ -156,33 +161,58 @@ __device__ inline void st_wg(u32* p, u32 v) { __hip_atomic_store(p, v, __ATOMIC_
 __device__ inline int ld_ag(const int32_t* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 __device__ inline void st_ag(int32_t* p, int v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 
-// Union-find in LDS over tile positions: union by minimum, path halving.
-// A root is linked with compare-and-swap only while it is still a root, so a
-// tree never loses members; path halving only ever writes an ancestor into a
-// non-root.  Concurrent finds and links are therefore safe.
-__device__ inline u32 lfind(u32* par, u32 x) {
+// Union-find in LDS over tile positions, 16-bit entries: union by minimum,
+// path halving.  A root is linked with compare-and-swap (on the 32-bit word
+// holding its entry) only while it is still a root, so a tree never loses
+// members; path halving only ever writes an ancestor into a non-root.
+// Concurrent finds and links are therefore safe.
+__device__ inline u32 ld16(const u16* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
+__device__ inline void st16(u16* p, u32 v) { __hip_atomic_store(p, (u16)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
+
+// link root b under a; false if b is no longer a root
+__device__ inline bool llink(u16* par, u32 a, u32 b) {
+  u32* w = reinterpret_cast<u32*>(par + (b & ~1u));
+  const int sh = (int)(b & 1u) * 16;
+  u32 old = ld_wg(w);
   for (;;) {
-    u32 p = ld_wg(&par[x]);
-    if (p == x) return x;
-    u32 g = ld_wg(&par[p]);
-    if (g == p) return p;
-    st_wg(&par[x], g);
-    x = g;
+    if (((old >> sh) & 0xFFFFu) != b) return false;
+    u32 nw = (old & ~(0xFFFFu << sh)) | (a << sh);
+    u32 prev = atomicCAS(w, old, nw);
+    if (prev == old) return true;
+    old = prev;  // the word changed (possibly only the other entry): look again
   }
 }
-__device__ inline void lunion(u32* par, u32 a, u32 b) {
+// unite the classes of a and b: both walks advance together, two levels
+// per step with path halving; the loads are unconditional (a walk that has
+// reached its root reads it again) so that the four of a step overlap
+__device__ inline void lunion(u16* par, u32 a, u32 b) {
   for (;;) {
-    a = lfind(par, a);
-    b = lfind(par, b);
-    if (a == b) return;
-    if (a > b) { u32 t = a; a = b; b = t; }
-    if (atomicCAS(&par[b], b, a) == b) return;  // else b was linked meanwhile: retry
+    for (;;) {
+      u32 pa = ld16(par + a), pb = ld16(par + b);
+      u32 ga = ld16(par + pa), gb = ld16(par + pb);
+      if (ga != pa) st16(par + a, ga);  // a is not a root: halve
+      if (gb != pb) st16(par + b, gb);
+      const bool fa = ga == pa, fb = gb == pb;  // pa / pb is a root
+      a = ga;
+      b = gb;
+      if (a == b) return;
+      if (fa && fb) break;
+    }
+    if (a > b) {
+      u32 t = a;
+      a = b;
+      b = t;
+    }
+    if (llink(par, a, b)) return;  // else b was linked meanwhile: retry
   }
 }
 // read-only walk to the root (no writes)
-__device__ inline u32 lroot(const u32* par, u32 x) {
-  u32 p = par[x];
-  while (p != x) { x = p; p = par[x]; }
+__device__ inline u32 lroot(const u16* par, u32 x) {
+  u32 p = ld16(par + x);
+  while (p != x) {
+    x = p;
+    p = ld16(par + x);
+  }
   return x;
 }
 
@@ -273,22 +303,29 @@ struct TileSmem {
   u64 st[T::NW];     // run starts
   u64 bflag[T::NW];  // roots whose component touches the tile border
   u64 rootm[T::NW];  // roots (position p with par[p] == p at a run start)
-  u64 lmask[T::NW];  // roots that hold their component's first pixel
-  u32 par[T::N];     // union-find over positions ly * TW + x
-  u16 last[T::NW];   // x of the last run start in words <= j of the row
+  // union-find over positions ly * TW + x (only run starts are used); once
+  // the roots are known, the root ordinal of every run start
+  alignas(8) u16 par[T::N];
   u16 bpre[T::NW];   // border roots before word (tile raster order)
   u16 ipre[T::NW];   // interior roots before word
-  int nb, nint;
-  int euler;
-  int uniform;       // 0: general tile; 1 + colour: every valid pixel has one colour
+  u16 spre[T::NW];   // run starts before word
+  int nb, nint, nruns;
 };
 
 template <class T>
-__device__ inline int run_start(const TileSmem<T>& s, int ly, int x) {
+__device__ inline int run_start(const TileSmem<T>& s, int ly, int x) {  // x of the run holding (ly, x)
+  const u64* row = &s.st[ly * T::WPR];
   int j = x >> 6;
-  u64 m = s.st[ly * T::WPR + j] & (~0ull >> (63 - (x & 63)));
-  if (m) return (j << 6) + 63 - clz64(m);
-  return s.last[ly * T::WPR + j - 1];  // j > 0: bit 0 of word 0 is always a start
+  u64 m = row[j] & (~0ull >> (63 - (x & 63)));
+  if (T::WPR > 1) {
+    const u64 mp = row[j > 0 ? j - 1 : 0];  // read ahead: the usual fallback
+    if (!m) {
+      m = mp;
+      j--;
+      while (!m) m = row[--j];  // ends: bit 0 of word 0 is always a start
+    }
+  }
+  return (j << 6) + 63 - clz64(m);
 }
 
 template <class T>
@@ -302,20 +339,29 @@ __device__ inline int iord_of(const TileSmem<T>& s, int r) {  // r: interior roo
   return s.ipre[wd] + popc64(~s.bflag[wd] & s.rootm[wd] & low_mask(r & 63));
 }
 
-// Phases 1-6: load + pack, runs, unite, flatten, border flags, roots, prefix.
-// Ends with a barrier; afterwards par[p] is the root position of every run
-// start p, bflag/rootm/bpre/ipre/nb/nint are valid.
+// Phases 1-5: load + pack + runs, unite, flatten, border flags and roots,
+// prefix counts.  Returns 1 + colour for a one-colour tile (nothing else is
+// computed then), else 0.  Ends with a barrier; afterwards par[p] is the root
+// position of every run start p, bflag/rootm/bpre/ipre/spre/nb/nint/nruns
+// are valid.
 template <class T>
 __device__ int tile_label(TileSmem<T>& s, const u8* img, int64_t pitch, int x0, int y0, int tw, int th,
                           bool vec_in) {
+  static_assert(T::NCH % 64 == 0 || T::NCH < 64, "whole waves per chunk loop");
   const int tid = threadIdx.x;
-  // 1. load bytes, 16 pixels per chunk -> 16 bits; vote on a one-colour tile
+  // 1. load bytes, 16 pixels per chunk -> 16 bits; run starts (the pixel
+  // before the chunk comes from the lane holding the previous chunk, or from
+  // memory at a wave's first lane); par[p] = p at every run start; vote on a
+  // one-colour tile
   bool all0 = true, all1 = true;
-  for (int c = tid; c < T::NCH; c += T::NT) {
-    int ly = c / T::CPR, cx = (c % T::CPR) * 16;
+  for (int c0 = 0; c0 < T::NCH; c0 += T::NT) {
+    const int c = c0 + tid;
+    if (c0 + (tid & ~63) >= T::NCH) break;  // whole waves leave together
+    const int ly = c / T::CPR, cc = c % T::CPR, cx = cc * 16;
+    const bool in = c < T::NCH && ly < th && cx < tw;
     u32 m = 0;
-    if (ly < th && cx < tw) {
-      const u8* src = img + (int64_t)(y0 + ly) * pitch + (x0 + cx);
+    const u8* src = img + (int64_t)(y0 + ly) * pitch + (x0 + cx);
+    if (in) {
       if (vec_in && cx + 16 <= tw) {
         uint4 v = *reinterpret_cast<const uint4*>(src);
         m = nz4(v.x) | (nz4(v.y) << 4) | (nz4(v.z) << 8) | (nz4(v.w) << 12);
@@ -324,58 +370,30 @@ __device__ int tile_label(TileSmem<T>& s, const u8* img, int64_t pitch, int x0, 
         for (int k = 0; k < n; k++) m |= (u32)(src[k] != 0) << k;
       }
     }
+    u32 prev = __shfl_up(m, 1, 64);
+    if (c >= T::NCH) continue;
     reinterpret_cast<u16*>(s.bits)[c] = (u16)m;
-    if (ly < th && cx < tw) {
-      u32 vm = (u32)valid_mask(0, tw - cx) & 0xFFFFu;
+    u32 e = 0;
+    if (in) {
+      u32 carry;
+      if (cc == 0) carry = ~m & 1u;
+      else if ((tid & 63) == 0) carry = src[-1] != 0;
+      else carry = prev >> 15;
+      const u32 vm = (u32)valid_mask(0, tw - cx) & 0xFFFFu;
+      e = (m ^ ((m << 1) | carry)) & vm;
       all0 = all0 && (m & vm) == 0;
       all1 = all1 && (m & vm) == vm;
+      const u32 p0 = (u32)(ly * T::TW + cx);
+      for (u32 t = e; t; t &= t - 1) s.par[p0 + (u32)ctz32(t)] = (u16)(p0 + (u32)ctz32(t));
     }
+    reinterpret_cast<u16*>(s.st)[c] = (u16)e;
   }
   for (int i = tid; i < T::NW; i += T::NT) s.bflag[i] = 0;
   const int u0 = __syncthreads_and(all0);
   const int u1 = __syncthreads_and(all1);
-  if (u0 || u1) {
-    // one component covering the tile: its first pixel (0, 0) is the only
-    // run start that matters; callers take their one-colour path
-    if (tid == 0) {
-      s.uniform = u1 ? 2 : 1;
-      s.nb = 1;
-      s.nint = 0;
-    }
-    __syncthreads();
-    return u1 ? 2 : 1;
-  }
+  if (u0 || u1) return u1 ? 2 : 1;
 
-  // 2. run starts, 16 pixels per chunk; par[p] = p at every run start (the
-  // only entries ever read); last start per word, one row per thread
-  for (int c = tid; c < T::NCH; c += T::NT) {
-    int ly = c / T::CPR, cc = c % T::CPR;
-    const u16* b16 = reinterpret_cast<const u16*>(s.bits);
-    u32 b = b16[c];
-    u32 carry = cc ? (u32)(b16[c - 1] >> 15) : (~b & 1u);
-    u32 e = (b ^ ((b << 1) | carry)) & (u32)valid_mask(0, tw - cc * 16) & 0xFFFFu;
-    if (ly >= th) e = 0;
-    reinterpret_cast<u16*>(s.st)[c] = (u16)e;
-    const u32 p0 = (u32)(ly * T::TW + cc * 16);
-    while (e) {
-      u32 p = p0 + (u32)ctz32(e);
-      e &= e - 1;
-      s.par[p] = p;
-    }
-  }
-  for (int ly = tid; ly < T::TH; ly += T::NT) {
-    int lastx = 0;
-    for (int j = 0; j < T::WPR; j++) {
-      u64 b = s.bits[ly * T::WPR + j];
-      u64 carry = j ? (s.bits[ly * T::WPR + j - 1] >> 63) : (~b & 1ull);
-      u64 e = (b ^ ((b << 1) | carry)) & valid_mask(j, tw);
-      if (e) lastx = j * 64 + 63 - clz64(e);
-      s.last[ly * T::WPR + j] = (u16)lastx;
-    }
-  }
-  __syncthreads();
-
-  // 3. unite runs of rows ly-1, ly (all row pairs at once)
+  // 2. unite runs of rows ly-1, ly (all row pairs at once)
   for (int c = tid; c < T::NCH; c += T::NT) {
     int ly = c / T::CPR, cc = c % T::CPR;
     if (ly == 0 || ly >= th || cc * 16 >= tw) continue;
@@ -386,30 +404,23 @@ __device__ int tile_label(TileSmem<T>& s, const u8* img, int64_t pitch, int x0, 
     u64 m0p = j ? B0[j - 1] : 0ull, m1p = j ? B1[j - 1] : 0ull;
     u64 m0n = j + 1 < T::WPR ? B0[j + 1] : 0ull, m1n = j + 1 < T::WPR ? B1[j + 1] : 0ull;
     PairMasks pm = pair_masks(m0, m1, m0p, m1p, m0n, m1n, valid_mask(j, tw), j > 0);
-    u32 vv = (u32)(pm.vert >> sh) & 0xFFFFu;
-    u32 da = (u32)(pm.da >> sh) & 0xFFFFu;
-    u32 db = (u32)(pm.db >> sh) & 0xFFFFu;
+    // one loop over all union points of the chunk: bits 0-15 vertical,
+    // 16-31 diagonal up-right, 32-47 diagonal up-left
+    u64 pts = ((pm.vert >> sh) & 0xFFFFull) | (((pm.da >> sh) & 0xFFFFull) << 16) |
+              (((pm.db >> sh) & 0xFFFFull) << 32);
     const u32 r0 = (u32)(ly * T::TW), r1 = (u32)((ly - 1) * T::TW);
     const int xb = j * 64 + sh;
-    while (vv) {
-      int x = xb + ctz32(vv);
-      vv &= vv - 1;
-      lunion(s.par, r0 + run_start(s, ly, x), r1 + run_start(s, ly - 1, x));
-    }
-    while (da) {
-      int x = xb + ctz32(da);
-      da &= da - 1;
-      lunion(s.par, r0 + run_start(s, ly, x), r1 + run_start(s, ly - 1, x + 1));
-    }
-    while (db) {
-      int x = xb + ctz32(db);
-      db &= db - 1;
-      lunion(s.par, r0 + run_start(s, ly, x), r1 + run_start(s, ly - 1, x - 1));
+    while (pts) {
+      const int k = __builtin_ctzll(pts);
+      pts &= pts - 1;
+      const int x = xb + (k & 15);
+      const int xu = x + (k >> 4 == 1) - (k >> 4 == 2);
+      lunion(s.par, r0 + run_start(s, ly, x), r1 + run_start(s, ly - 1, xu));
     }
   }
   __syncthreads();
 
-  // 4. flatten: every run start points at its root (own entry written only)
+  // 3. flatten: every run start points at its root (own entry written only)
   for (int c = tid; c < T::NCH; c += T::NT) {
     int ly = c / T::CPR, cc = c % T::CPR;
     if (ly >= th) continue;
@@ -418,12 +429,12 @@ __device__ int tile_label(TileSmem<T>& s, const u8* img, int64_t pitch, int x0, 
     while (m) {
       u32 p = (u32)(ly * T::TW + j * 64 + sh + ctz32(m));
       m &= m - 1;
-      s.par[p] = lroot(s.par, p);
+      st16(&s.par[p], lroot(s.par, p));
     }
   }
   __syncthreads();
 
-  // 5. roots of components touching the tile border
+  // 4. roots of components touching the tile border; root masks
   for (int t = tid; t < 2 * T::CPR + 2 * T::TH; t += T::NT) {
     if (t < 2 * T::CPR) {  // top / bottom row, one chunk each
       int ly = t < T::CPR ? 0 : th - 1;
@@ -445,9 +456,6 @@ __device__ int tile_label(TileSmem<T>& s, const u8* img, int64_t pitch, int x0, 
       atomicOr(&s.bflag[r >> 6], 1ull << (r & 63));
     }
   }
-  __syncthreads();
-
-  // 6. root masks
   for (int c = tid; c < T::NCH; c += T::NT) {
     int ly = c / T::CPR, cc = c % T::CPR;
     int j = cc >> 2, sh = (cc & 3) * 16;
@@ -463,33 +471,41 @@ __device__ int tile_label(TileSmem<T>& s, const u8* img, int64_t pitch, int x0, 
   }
   __syncthreads();
 
-  // 7. exclusive prefix counts of border / interior roots over words
+  // 5. exclusive prefix counts of border roots, interior roots and run
+  // starts over words
   if (tid < 64) {
-    u32 cb = 0, ci = 0;
+    u32 cb = 0, ci = 0, cs = 0;
     for (int base = 0; base < T::NW; base += 64) {
       int wd = base + tid;
       u64 rm = wd < T::NW ? s.rootm[wd] : 0ull;
       u64 bf = wd < T::NW ? s.bflag[wd] : 0ull;
       u32 nb = (u32)popc64(rm & bf), ni = (u32)popc64(rm & ~bf);
       u32 v = nb | (ni << 16);  // both counts <= 4096 per 64 words
-      u32 inc = v;
+      u32 vs = wd < T::NW ? (u32)popc64(s.st[wd]) : 0u;
+      u32 inc = v, incs = vs;
       for (int d = 1; d < 64; d <<= 1) {
         u32 t = __shfl_up(inc, d, 64);
-        if (tid >= d) inc += t;
+        u32 ts = __shfl_up(incs, d, 64);
+        if (tid >= d) {
+          inc += t;
+          incs += ts;
+        }
       }
       u32 exc = inc - v;
       if (wd < T::NW) {
         s.bpre[wd] = (u16)(cb + (exc & 0xFFFFu));
         s.ipre[wd] = (u16)(ci + (exc >> 16));
+        s.spre[wd] = (u16)(cs + incs - vs);
       }
       u32 tot = __shfl(inc, 63, 64);
       cb += tot & 0xFFFFu;
       ci += tot >> 16;
+      cs += __shfl(incs, 63, 64);
     }
     if (tid == 0) {
       s.nb = (int)cb;
       s.nint = (int)ci;
-      s.uniform = 0;
+      s.nruns = (int)cs;
     }
   }
   __syncthreads();
@@ -628,6 +644,7 @@ __global__ void __launch_bounds__(256) k_tile_export(Src src, Work wk) {
       f.Sy = (int64_t)tw * ((int64_t)y0 * th + (int64_t)th * (th - 1) / 2);
       wk.gacc[nbase] = f;
       wk.nbt[gt] = 1;
+      wk.tinfo[gt] = uni;
     }
     for (int ly = tid; ly < th; ly += T::NT) wk.cgrid[d.c0 + (int64_t)(y0 + ly) * d.ntx + tx] = 0;
     for (int t = tid; t < 2 * T::TW + 2 * T::TH; t += T::NT) {
@@ -651,54 +668,75 @@ __global__ void __launch_bounds__(256) k_tile_export(Src src, Work wk) {
     return;
   }
 
-  // 8. border node records, interior counts per row, accumulator init
-  for (int wd = tid; wd < T::NW; wd += T::NT) {
-    int ly = wd / T::WPR, j = wd % T::WPR;
-    u64 bm = s.rootm[wd] & s.bflag[wd];
-    u64 im = s.rootm[wd] & ~s.bflag[wd];
-    int ib_row = s.ipre[wd] - s.ipre[ly * T::WPR];
-    while (bm) {
-      int k = __builtin_ctzll(bm);
-      bm &= bm - 1;
+  // 6. root ordinal of every run start (border roots first, then interior
+  // roots) into par and into the tile state for K6; border node records;
+  // interior roots per row
+  const int nb = s.nb;
+  u16* to = wk.tord + gt * T::N;
+  for (int c = tid; c < T::NCH; c += T::NT) {
+    int ly = c / T::CPR, cc = c % T::CPR;
+    if (ly >= th) continue;
+    int j = cc >> 2, sh = (cc & 3) * 16;
+    int wd = ly * T::WPR + j;
+    u64 stw = s.st[wd];
+    int rank = s.spre[wd] + popc64(stw & low_mask(sh));
+    for (u32 m = (u32)(stw >> sh) & 0xFFFFu; m; m &= m - 1) {
+      int p = ly * T::TW + j * 64 + sh + ctz32(m);
+      u32 r = s.par[p];
+      int o = ((s.bflag[r >> 6] >> (r & 63)) & 1ull) ? bidx_of<T>(s, (int)r) : nb + iord_of<T>(s, (int)r);
+      s.par[p] = (u16)o;  // only this thread reads this entry from here on
+      to[rank++] = (u16)o;
+    }
+    const u64 bmw = s.rootm[wd] & s.bflag[wd];
+    const u64 imw = s.rootm[wd] & ~s.bflag[wd];
+    const int ib_row = s.ipre[wd] - s.ipre[ly * T::WPR];
+    for (u32 m = (u32)(bmw >> sh) & 0xFFFFu; m; m &= m - 1) {
+      int k = sh + ctz32(m);
       int x = j * 64 + k;
-      int bi = s.bpre[wd] + popc64(s.rootm[wd] & s.bflag[wd] & low_mask(k));
+      int bi = s.bpre[wd] + popc64(bmw & low_mask(k));
       int64_t node = nbase + bi;
       int32_t key = (int32_t)((int64_t)(y0 + ly) * d.w + x0 + x);
       wk.gpar[node] = (int32_t)node;
       wk.gkey[node] = key;
       wk.gminkey[node] = key;
-      wk.grank[node] = (ib_row + popc64(im & low_mask(k))) | (ly << 16);
+      wk.grank[node] = (ib_row + popc64(imw & low_mask(k))) | (ly << 16);
       acc_init(bacc[bi]);
     }
   }
   for (int ly = tid; ly < th; ly += T::NT) {
-    int cnt = 0;
-    for (int j = 0; j < T::WPR; j++) cnt += popc64(s.rootm[ly * T::WPR + j] & ~s.bflag[ly * T::WPR + j]);
-    wk.cgrid[d.c0 + (int64_t)(y0 + ly) * d.ntx + tx] = cnt;
+    int next = ly + 1 < T::TH ? s.ipre[(ly + 1) * T::WPR] : s.nint;
+    wk.cgrid[d.c0 + (int64_t)(y0 + ly) * d.ntx + tx] = next - s.ipre[ly * T::WPR];
   }
-  if (tid == 0) wk.nbt[gt] = s.nb;
+  u64* ts = wk.tstate + gt * 3 * T::NW;
+  for (int i = tid; i < 3 * T::NW; i += T::NT) {
+    int k = i / T::NW, wd = i % T::NW;
+    ts[i] = k == 0 ? s.bits[wd] : (k == 1 ? s.rootm[wd] : (s.rootm[wd] & s.bflag[wd]));
+  }
+  if (tid == 0) {
+    wk.nbt[gt] = nb;
+    wk.tinfo[gt] = s.nruns << 2;
+  }
   __syncthreads();
 
-  // 9. partial features of border components
+  // 7. partial features of border components
   for (int c = tid; c < T::NCH; c += T::NT) {
     int ly = c / T::CPR, cc = c % T::CPR;
     if (ly >= th) continue;
     for_segments<T>(s, ly, cc, tw, [&](int start, int a, int b) {
-      u32 r = s.par[ly * T::TW + start];
-      if (s.bflag[r >> 6] & (1ull << (r & 63))) acc_add(bacc[bidx_of<T>(s, (int)r)], ly, a, b);
+      int o = s.par[ly * T::TW + start];
+      if (o < nb) acc_add(bacc[o], ly, a, b);
     });
   }
   __syncthreads();
 
-  // 10. write partial features and the border arrays
-  for (int wd = tid; wd < T::NW; wd += T::NT) {
-    int ly = wd / T::WPR, j = wd % T::WPR;
-    u64 bm = s.rootm[wd] & s.bflag[wd];
-    while (bm) {
-      int k = __builtin_ctzll(bm);
-      bm &= bm - 1;
-      int bi = s.bpre[wd] + popc64(s.rootm[wd] & s.bflag[wd] & low_mask(k));
-      (void)j;
+  // 8. write partial features and the border arrays
+  for (int c = tid; c < T::NCH; c += T::NT) {
+    int ly = c / T::CPR, cc = c % T::CPR;
+    int j = cc >> 2, sh = (cc & 3) * 16;
+    int wd = ly * T::WPR + j;
+    const u64 bmw = s.rootm[wd] & s.bflag[wd];
+    for (u32 m = (u32)(bmw >> sh) & 0xFFFFu; m; m &= m - 1) {
+      int bi = s.bpre[wd] + popc64(bmw & low_mask(sh + ctz32(m)));
       wk.gacc[nbase + bi] = acc_abs(bacc[bi], ly, x0, y0);
     }
   }
@@ -708,17 +746,14 @@ __global__ void __launch_bounds__(256) k_tile_export(Src src, Work wk) {
       int x = t % T::TW;
       int ly = bottom ? th - 1 : 0;
       u16 v = 0xFFFFu;
-      if (x < tw) v = (u16)bidx_of<T>(s, (int)s.par[ly * T::TW + run_start(s, ly, x)]);
+      if (x < tw) v = s.par[ly * T::TW + run_start(s, ly, x)];
       (bottom ? wk.bidx_bot : wk.bidx_top)[gt * T::TW + x] = v;
     } else {
       int k = t - 2 * T::TW;
       int right = k >= T::TH;
       int ly = k % T::TH;
       u16 v = 0xFFFFu;
-      if (ly < th) {
-        int x = right ? run_start(s, ly, tw - 1) : 0;
-        v = (u16)bidx_of<T>(s, (int)s.par[ly * T::TW + x]);
-      }
+      if (ly < th) v = s.par[ly * T::TW + (right ? run_start(s, ly, tw - 1) : 0)];
       (right ? wk.bidx_right : wk.bidx_left)[gt * T::TH + ly] = v;
     }
   }
@@ -1162,13 +1197,55 @@ __global__ void __launch_bounds__(64) k_emit_border(Src src, Work wk) {
 }
 
 // ---------------------------------------------------------------------------
-// K6: relabel the tile, write labels and the tables of the components it owns
+// K6: relabel the tile, write labels and the tables of the components it
+// owns.  Works from the tile state K1 left (no image reload, no union-find).
+
+template <class T>
+struct EmitSmem {
+  u64 bits[T::NW];
+  u64 st[T::NW];       // run starts
+  u64 rootm[T::NW];    // roots
+  u64 broot[T::NW];    // roots of components touching the tile border
+  u64 lmask[T::NW];    // roots that hold their component's first pixel
+  u16 spre[T::NW];     // run starts before word (tile raster order)
+  u16 bpre[T::NW];     // border roots before word
+  u16 ipre[T::NW];     // interior roots before word
+  u16 ordr[T::N];      // root ordinal by run rank
+  int32_t canon[T::N]; // canonical id by root ordinal
+  int32_t rowbase[T::TH];  // first canonical id of the row's components starting here
+  int nb, nint, nruns, euler;
+};
+
+template <class T>
+__device__ inline int run_rank(const EmitSmem<T>& s, int ly, int x) {  // run holding pixel (ly, x)
+  int wd = ly * T::WPR + (x >> 6);
+  return s.spre[wd] + popc64(s.st[wd] & (~0ull >> (63 - (x & 63)))) - 1;
+}
+
+// Segments of one 16-pixel chunk: calls f(run_rank, seg_begin, seg_end).
+template <class T, class Fn>
+__device__ inline void for_runs(const EmitSmem<T>& s, int ly, int cc, int tw, Fn f) {
+  int cs = cc * 16;
+  if (cs >= tw) return;
+  int ce = cs + 16 < tw ? cs + 16 : tw;
+  int j = cc >> 2, sh = (cc & 3) * 16;
+  u32 m = ((u32)(s.st[ly * T::WPR + j] >> sh) & 0xFFFFu) & ~1u;
+  int rank = run_rank(s, ly, cs);
+  int x = cs;
+  for (;;) {
+    int nx = m ? cs + ctz32(m) : ce;
+    f(rank, x, nx);
+    if (!m) break;
+    m &= m - 1;
+    rank++;
+    x = nx;
+  }
+}
 
 template <class T, class Src>
 __global__ void __launch_bounds__(256) k_tile_emit(Src src, Work wk) {
-  __shared__ TileSmem<T> s;
+  __shared__ EmitSmem<T> s;
   __shared__ Acc iacc[T::CAPI];
-  __shared__ int32_t bcanon[T::BCAP];
   const int64_t gt = blockIdx.x;
   const ImgDesc& d = src.by_tile(gt);
   const int64_t lt = gt - d.tile0;
@@ -1177,13 +1254,12 @@ __global__ void __launch_bounds__(256) k_tile_emit(Src src, Work wk) {
   const int tw = d.w - x0 < T::TW ? d.w - x0 : T::TW;
   const int th = d.h - y0 < T::TH ? d.h - y0 : T::TH;
   const int tid = threadIdx.x;
-
-  const int uni = tile_label<T>(s, d.img, d.pitch, x0, y0, tw, th, (d.flags & DF_VEC_IN) != 0);
   const int64_t nbase = tile_node_base<T>(d, lt);
+  const int info = wk.tinfo[gt];
 
-  if (uni) {
+  if (info & 3) {
     // one-colour tile: its single component is border node slot 0
-    const int col = uni - 1;
+    const int col = (info & 3) - 1;
     const int node = (int)nbase;
     const int32_t canon = wk.rcanon[wk.gpar[node]];
     if (tid == 0 && (wk.grank[node] & (int)HI)) {  // the component starts here
@@ -1214,131 +1290,118 @@ __global__ void __launch_bounds__(256) k_tile_emit(Src src, Work wk) {
     return;
   }
 
+  // 1. tile state, root ordinals of the runs, row bases; canonical ids of the
+  // border roots (HI marks the ones holding their component's first pixel)
+  const int nruns = info >> 2;
+  const int nbt = wk.nbt[gt];
+  const u64* ts = wk.tstate + gt * 3 * T::NW;
+  for (int i = tid; i < 3 * T::NW; i += T::NT) {
+    u64 v = ts[i];
+    int k = i / T::NW, wd = i % T::NW;
+    if (k == 0) s.bits[wd] = v;
+    else if (k == 1) s.rootm[wd] = v;
+    else s.broot[wd] = v;
+  }
+  const u16* to = wk.tord + gt * T::N;
+  for (int r = tid; r < nruns; r += T::NT) s.ordr[r] = to[r];
+  for (int ly = tid; ly < th; ly += T::NT) s.rowbase[ly] = wk.cgrid[d.c0 + (int64_t)(y0 + ly) * d.ntx + tx];
+  for (int bi = tid; bi < nbt; bi += T::NT) {
+    int node = (int)(nbase + bi);
+    int g = wk.grank[node];
+    s.canon[bi] = wk.rcanon[wk.gpar[node]] | (g & (int)HI);
+  }
   if (tid == 0) s.euler = 0;
-  // 8. canonical ids of border roots; leader mask (interior roots lead)
-  for (int wd = tid; wd < T::NW; wd += T::NT) s.lmask[wd] = s.rootm[wd] & ~s.bflag[wd];
-  __syncthreads();
-  for (int wd = tid; wd < T::NW; wd += T::NT) {
-    u64 bm = s.rootm[wd] & s.bflag[wd];
-    u64 lead = 0;
-    while (bm) {
-      int k = __builtin_ctzll(bm);
-      bm &= bm - 1;
-      int bi = s.bpre[wd] + popc64(s.rootm[wd] & s.bflag[wd] & low_mask(k));
-      int node = (int)(nbase + bi);
-      int r = wk.gpar[node];
-      bcanon[bi] = wk.rcanon[r];
-      if (wk.grank[node] & (int)HI) lead |= 1ull << k;
-    }
-    s.lmask[wd] |= lead;
-  }
   __syncthreads();
 
-  // 9. canonical id into every root entry (HI marks a resolved entry)
-  int e_local = 0;
+  // 2. run starts; interior roots lead
   for (int wd = tid; wd < T::NW; wd += T::NT) {
     int ly = wd / T::WPR, j = wd % T::WPR;
-    u64 rm = s.rootm[wd];
-    if (!rm) continue;
-    int rowlead = 0;
-    for (int jj = 0; jj < j; jj++) rowlead += popc64(s.lmask[ly * T::WPR + jj]);
-    int32_t base = wk.cgrid[d.c0 + (int64_t)(y0 + ly) * d.ntx + tx];
-    while (rm) {
-      int k = __builtin_ctzll(rm);
-      rm &= rm - 1;
-      int p = ly * T::TW + j * 64 + k;
-      int32_t canon;
-      if (s.bflag[wd] & (1ull << k)) canon = bcanon[bidx_of<T>(s, p)];
-      else canon = base + rowlead + popc64(s.lmask[wd] & low_mask(k));
-      if (s.lmask[wd] & (1ull << k)) e_local += ((s.bits[wd] >> k) & 1ull) ? 1 : -1;
-      s.par[p] = (u32)canon | HI;
+    u64 b = s.bits[wd];
+    u64 carry = j ? (s.bits[wd - 1] >> 63) : (~b & 1ull);
+    u64 e = (b ^ ((b << 1) | carry)) & valid_mask(j, tw);
+    s.st[wd] = ly < th ? e : 0ull;
+    s.lmask[wd] = s.rootm[wd] & ~s.broot[wd];
+  }
+  __syncthreads();
+
+  // 3. exclusive prefix counts over words: border roots, interior roots, run starts
+  if (tid < 64) {
+    u32 cb = 0, ci = 0, cs = 0;
+    for (int base = 0; base < T::NW; base += 64) {
+      int wd = base + tid;
+      u64 rm = wd < T::NW ? s.rootm[wd] : 0ull;
+      u64 bm = wd < T::NW ? s.broot[wd] : 0ull;
+      u32 v = (u32)popc64(bm) | ((u32)popc64(rm & ~bm) << 16);
+      u32 vs = wd < T::NW ? (u32)popc64(s.st[wd]) : 0u;
+      u32 inc = v, incs = vs;
+      for (int dl = 1; dl < 64; dl <<= 1) {
+        u32 t = __shfl_up(inc, dl, 64);
+        u32 t2 = __shfl_up(incs, dl, 64);
+        if (tid >= dl) {
+          inc += t;
+          incs += t2;
+        }
+      }
+      if (wd < T::NW) {
+        u32 exc = inc - v;
+        s.bpre[wd] = (u16)(cb + (exc & 0xFFFFu));
+        s.ipre[wd] = (u16)(ci + (exc >> 16));
+        s.spre[wd] = (u16)(cs + incs - vs);
+      }
+      u32 tot = __shfl(inc, 63, 64);
+      cb += tot & 0xFFFFu;
+      ci += tot >> 16;
+      cs += __shfl(incs, 63, 64);
+    }
+    if (tid == 0) {
+      s.nb = (int)cb;
+      s.nint = (int)ci;
+      s.nruns = (int)cs;
     }
   }
   __syncthreads();
 
-  // 10. features of interior components, CAPI at a time; their colour / parent
-  const int nint = s.nint;
-  for (int k0 = 0; k0 < nint; k0 += T::CAPI) {
-    for (int i = tid; i < T::CAPI; i += T::NT) acc_init(iacc[i]);
-    __syncthreads();
-    for (int c = tid; c < T::NCH; c += T::NT) {
-      int ly = c / T::CPR, cc = c % T::CPR;
-      if (ly >= th) continue;
-      for_segments<T>(s, ly, cc, tw, [&](int start, int a, int b) {
-        int p = ly * T::TW + start;
-        u32 v = s.par[p];
-        int r = (v & HI) ? p : (int)v;
-        if (s.bflag[r >> 6] & (1ull << (r & 63))) return;
-        int o = iord_of<T>(s, r) - k0;
-        if (o >= 0 && o < T::CAPI) acc_add(iacc[o], ly, a, b);
-      });
-    }
-    __syncthreads();
-    for (int wd = tid; wd < T::NW; wd += T::NT) {
-      int ly = wd / T::WPR, j = wd % T::WPR;
-      u64 im = s.rootm[wd] & ~s.bflag[wd];
-      while (im) {
-        int k = __builtin_ctzll(im);
-        im &= im - 1;
-        int p = ly * T::TW + j * 64 + k;
-        int o = iord_of<T>(s, p) - k0;
-        if (o < 0 || o >= T::CAPI) continue;
-        int32_t canon = (int32_t)(s.par[p] & ~HI);
-        if (canon >= d.cap) continue;
-        if (d.feat) d.feat[canon] = acc_abs(iacc[o], ly, x0, y0);
-        if (d.color) d.color[canon] = (u8)((s.bits[wd] >> k) & 1ull);
-        if (d.parent) {
-          int x = j * 64 + k;  // interior: x > 0
-          int q = ly * T::TW + run_start(s, ly, x - 1);
-          u32 v = s.par[q];
-          d.parent[canon] = (int32_t)(((v & HI) ? v : s.par[v]) & ~HI);
-        }
-      }
-    }
-    __syncthreads();
-  }
-
-  // 11. colour / parent of border components whose first pixel is here
-  for (int wd = tid; wd < T::NW; wd += T::NT) {
-    int ly = wd / T::WPR, j = wd % T::WPR;
-    u64 bl = s.rootm[wd] & s.bflag[wd] & s.lmask[wd];
-    while (bl) {
-      int k = __builtin_ctzll(bl);
-      bl &= bl - 1;
-      int p = ly * T::TW + j * 64 + k;
-      int32_t canon = (int32_t)(s.par[p] & ~HI);
-      if (canon >= d.cap) continue;
-      if (d.color) d.color[canon] = (u8)((s.bits[wd] >> k) & 1ull);
-      if (d.parent) {
-        int x = j * 64 + k;
-        int32_t pc;
-        if (x > 0) {
-          int q = ly * T::TW + run_start(s, ly, x - 1);
-          u32 v = s.par[q];
-          pc = (int32_t)(((v & HI) ? v : s.par[v]) & ~HI);
-        } else if (tx > 0) {
-          int nl = col_node<T>(wk, d, tx - 1, y0 + ly, true);
-          pc = wk.rcanon[wk.gpar[nl]];
-        } else {
-          pc = 0;
-        }
-        d.parent[canon] = pc;
-      }
-    }
-  }
-  __syncthreads();
-
-  // 12. every run start takes its root's canonical id
+  // 4. border roots holding their component's first pixel join the leaders
   for (int c = tid; c < T::NCH; c += T::NT) {
     int ly = c / T::CPR, cc = c % T::CPR;
-    if (ly >= th) continue;
     int j = cc >> 2, sh = (cc & 3) * 16;
-    u32 m = (u32)(s.st[ly * T::WPR + j] >> sh) & 0xFFFFu;
-    while (m) {
-      int p = ly * T::TW + j * 64 + sh + ctz32(m);
-      m &= m - 1;
-      u32 v = s.par[p];
-      if (!(v & HI)) s.par[p] = s.par[v];
+    int wd = ly * T::WPR + j;
+    const u64 bmw = s.broot[wd];
+    u32 lead = 0;
+    for (u32 m = (u32)(bmw >> sh) & 0xFFFFu; m; m &= m - 1) {
+      int k = ctz32(m);
+      int bi = s.bpre[wd] + popc64(bmw & low_mask(sh + k));
+      int32_t cv = s.canon[bi];
+      if (cv & (int32_t)HI) {
+        lead |= 1u << k;
+        s.canon[bi] = cv & ~(int32_t)HI;
+      }
+    }
+    if (lead) reinterpret_cast<u16*>(s.lmask)[c] |= (u16)lead;
+  }
+  __syncthreads();
+
+  // 5. canonical ids of interior roots (row base + rank among the row's
+  // leaders); Euler number over the components that start here
+  const int nb = s.nb;
+  int e_local = 0;
+  for (int c = tid; c < T::NCH; c += T::NT) {
+    int ly = c / T::CPR, cc = c % T::CPR;
+    int j = cc >> 2, sh = (cc & 3) * 16;
+    int wd = ly * T::WPR + j;
+    u32 lm = reinterpret_cast<const u16*>(s.lmask)[c];
+    u32 b16 = reinterpret_cast<const u16*>(s.bits)[c];
+    e_local += popc64(lm & b16) - popc64(lm & ~b16 & 0xFFFFu);
+    const u64 imw = s.rootm[wd] & ~s.broot[wd];
+    u32 im = (u32)(imw >> sh) & 0xFFFFu;
+    if (!im) continue;
+    int rowlead = popc64(s.lmask[wd] & low_mask(sh));
+    for (int jj = 0; jj < j; jj++) rowlead += popc64(s.lmask[ly * T::WPR + jj]);
+    const int32_t base = s.rowbase[ly] + rowlead;
+    for (; im; im &= im - 1) {
+      int k = ctz32(im);
+      int ii = s.ipre[wd] + popc64(imw & low_mask(sh + k));
+      s.canon[nb + ii] = base + popc64(lm & ((1u << k) - 1u));
     }
   }
   atomicAdd(&s.euler, e_local);
@@ -1346,19 +1409,75 @@ __global__ void __launch_bounds__(256) k_tile_emit(Src src, Work wk) {
   if (tid == 0 && s.euler != 0 && d.counts)
     atomicAdd(reinterpret_cast<unsigned long long*>(&d.counts[1]), (unsigned long long)(int64_t)s.euler);
 
-  // 13. label image, four pixels per thread
+  // 6. features of interior components, CAPI at a time; their colour / parent
+  const int nint = s.nint;
+  for (int k0 = 0; k0 < nint; k0 += T::CAPI) {
+    for (int i = tid; i < T::CAPI; i += T::NT) acc_init(iacc[i]);
+    __syncthreads();
+    for (int c = tid; c < T::NCH; c += T::NT) {
+      int ly = c / T::CPR, cc = c % T::CPR;
+      if (ly >= th) continue;
+      for_runs<T>(s, ly, cc, tw, [&](int rank, int a, int b) {
+        int o = (int)s.ordr[rank] - nb - k0;
+        if (o >= 0 && o < T::CAPI) acc_add(iacc[o], ly, a, b);
+      });
+    }
+    __syncthreads();
+    for (int c = tid; c < T::NCH; c += T::NT) {
+      int ly = c / T::CPR, cc = c % T::CPR;
+      int j = cc >> 2, sh = (cc & 3) * 16;
+      int wd = ly * T::WPR + j;
+      const u64 imw = s.rootm[wd] & ~s.broot[wd];
+      for (u32 im = (u32)(imw >> sh) & 0xFFFFu; im; im &= im - 1) {
+        int k = sh + ctz32(im);
+        int ii = s.ipre[wd] + popc64(imw & low_mask(k));
+        int o = ii - k0;
+        if (o < 0 || o >= T::CAPI) continue;
+        int32_t canon = s.canon[nb + ii];
+        if (canon >= d.cap) continue;
+        if (d.feat) d.feat[canon] = acc_abs(iacc[o], ly, x0, y0);
+        if (d.color) d.color[canon] = (u8)((s.bits[wd] >> k) & 1ull);
+        if (d.parent) d.parent[canon] = s.canon[s.ordr[run_rank(s, ly, j * 64 + k - 1)]];  // interior: x > 0
+      }
+    }
+    __syncthreads();
+  }
+
+  // 7. colour / parent of border components whose first pixel is here
+  for (int c = tid; c < T::NCH; c += T::NT) {
+    int ly = c / T::CPR, cc = c % T::CPR;
+    int j = cc >> 2, sh = (cc & 3) * 16;
+    int wd = ly * T::WPR + j;
+    const u64 bmw = s.broot[wd];
+    for (u32 bl = (u32)((bmw & s.lmask[wd]) >> sh) & 0xFFFFu; bl; bl &= bl - 1) {
+      int k = sh + ctz32(bl);
+      int32_t canon = s.canon[s.bpre[wd] + popc64(bmw & low_mask(k))];
+      if (canon >= d.cap) continue;
+      if (d.color) d.color[canon] = (u8)((s.bits[wd] >> k) & 1ull);
+      if (d.parent) {
+        int x = j * 64 + k;
+        int32_t pc;
+        if (x > 0) pc = s.canon[s.ordr[run_rank(s, ly, x - 1)]];
+        else if (tx > 0) pc = wk.rcanon[wk.gpar[col_node<T>(wk, d, tx - 1, y0 + ly, true)]];
+        else pc = 0;
+        d.parent[canon] = pc;
+      }
+    }
+  }
+
+  // 8. label image, four pixels per thread
   if (d.labels) {
     const bool vec = (d.flags & DF_VEC_LAB) != 0;
     for (int q = tid; q < T::TH * (T::TW / 4); q += T::NT) {
       int ly = q / (T::TW / 4), x = (q % (T::TW / 4)) * 4;
       if (ly >= th || x >= tw) continue;
-      int st0 = run_start(s, ly, x);
+      int r = run_rank(s, ly, x);
       int32_t lab[4];
-      int32_t cur = (int32_t)(s.par[ly * T::TW + st0] & ~HI);
+      int32_t cur = s.canon[s.ordr[r]];
       u64 sw = s.st[ly * T::WPR + (x >> 6)] >> (x & 63);
       lab[0] = cur;
       for (int k = 1; k < 4; k++) {
-        if ((sw >> k) & 1ull) cur = (int32_t)(s.par[ly * T::TW + x + k] & ~HI);
+        if ((sw >> k) & 1ull) cur = s.canon[s.ordr[++r]];
         lab[k] = cur;
       }
       int32_t* dst = d.labels + (int64_t)(y0 + ly) * d.w + x0 + x;
@@ -1381,7 +1500,7 @@ struct Layout {
   int64_t tiles, nodes, cells, blocks;
   size_t off_gpar, off_gkey, off_gminkey, off_grank, off_rcanon, off_gacc, off_nbt;
   size_t off_btop, off_bbot, off_bleft, off_bright, off_bitstop, off_bitsbot, off_bitslr;
-  size_t off_cgrid, off_bsum, bytes;
+  size_t off_cgrid, off_bsum, off_tinfo, off_tstate, off_tord, bytes;
 };
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -1415,6 +1534,9 @@ inline Layout make_layout(int64_t tiles, int64_t nodes, int64_t cells, int64_t b
   L.off_bitslr = take(16 * (size_t)tiles);
   L.off_cgrid = take(4 * (size_t)cells);
   L.off_bsum = take(4 * (size_t)blocks);
+  L.off_tinfo = take(4 * (size_t)tiles);
+  L.off_tstate = take(8 * 3 * (size_t)tiles * T::NW);
+  L.off_tord = take(2 * (size_t)tiles * T::N);
   L.bytes = o;
   return L;
 }
@@ -1438,6 +1560,9 @@ inline Work make_work(const Layout& L, void* ws) {
   w.bits_lr = reinterpret_cast<u64*>(b + L.off_bitslr);
   w.cgrid = reinterpret_cast<int32_t*>(b + L.off_cgrid);
   w.bsum = reinterpret_cast<int32_t*>(b + L.off_bsum);
+  w.tinfo = reinterpret_cast<int32_t*>(b + L.off_tinfo);
+  w.tstate = reinterpret_cast<u64*>(b + L.off_tstate);
+  w.tord = reinterpret_cast<u16*>(b + L.off_tord);
   return w;
 }
 
