@@ -23,24 +23,27 @@
 //   k_tile_export : pack the tile to bits, extract runs, unite runs of
 //                   consecutive rows in LDS, find which local components touch
 //                   the tile border, export them as "border nodes" with their
-//                   partial features, and count interior components per row.
+//                   partial features, count interior components per row, and
+//                   leave the tile state (bits, root masks, the root ordinal of
+//                   every run) for k_tile_emit.  A one-colour tile skips the
+//                   union-find: one border node, features in closed form.
 //   k_border_merge: unite border nodes across tile edges (horizontal and
 //                   vertical seams, foreground diagonals across corners) and
-//                   background on the image border with the exterior node,
-//                   atomicMin union-find in HBM.
-//   k_flatten     : final root of every border node (full path compression).
-//   k_reduce_roots: the root takes the minimum raster key and the sum of the
-//                   partial features (LDS hash per group of tiles first;
-//                   k_reduce_direct is the variant with direct atomics).
+//                   background on the image border with the exterior node;
+//                   lock-free union-find in HBM (link by compare-and-swap).
+//   k_reduce_roots: point every border node at its root; the root takes the
+//                   minimum raster key and the sum of the partial features
+//                   (LDS hash per group of tiles first; k_reduce_direct is the
+//                   variant with direct atomics).
 //   k_leaders     : which border node holds its component's first pixel; rank
 //                   of that pixel among the components starting in the same
 //                   row of the same tile.
 //   k_scan_*      : exclusive scan of component starts over (row, tile column)
 //                   in raster order -> canonical id base of every such cell.
 //   k_emit_border : canonical id and features of components crossing tiles.
-//   k_tile_emit   : relabel the tile again (same code), write the label image,
-//                   features / colour / parent of every component it owns and
-//                   the Euler number contribution.
+//   k_tile_emit   : from the tile state: canonical id of every run, the label
+//                   image, features / colour / parent of every component the
+//                   tile owns and its Euler number contribution.
 //
 // Canonical ids: the exterior (background connected to the image border,
 // through a one-pixel background frame on all four sides) is 0; every other
@@ -158,7 +161,6 @@ __device__ inline u32 nz4(u32 d) {
 
 __device__ inline u32 ld_wg(const u32* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
 __device__ inline void st_wg(u32* p, u32 v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
-__device__ inline int ld_ag(const int32_t* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 __device__ inline void st_ag(int32_t* p, int v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 
 // Union-find in LDS over tile positions, 16-bit entries: union by minimum,
@@ -216,7 +218,8 @@ __device__ inline u32 lroot(const u16* par, u32 x) {
   return x;
 }
 
-// Union-find in HBM over border nodes (same scheme, agent scope).
+// Union-find in HBM over border nodes (same scheme; links and compression
+// writes at agent scope, reads through the caches).
 // Find with path compression.  Every entry points to a smaller index unless
 // it is a root, so both walks strictly decrease and end.  The second walk
 // points the entries above the root found at that root.
@@ -227,15 +230,23 @@ __device__ inline u32 lroot(const u16* par, u32 x) {
 // again, so no write can meet a link), only ever writes r < x, and stops at
 // the first index <= r.  Without concurrent unions all writes of a class
 // carry its final root.
+// A read may return an older value of an entry: that is an older ancestor
+// (entries only ever move up their tree), so walks stay correct; a node seen
+// as a root that has been linked meanwhile makes the link fail, and the
+// failed compare-and-swap returns the entry's current value, from which the
+// walk goes on (each failure climbs at least one level, so unions end).
+__device__ inline int ld_wk(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
 __device__ inline int gfind(int32_t* gp, int x) {
   int r = x;
-  int p = ld_ag(&gp[r]);
+  int p = ld_wk(&gp[r]);
   while (p != r) {
     r = p;
-    p = ld_ag(&gp[r]);
+    p = ld_wk(&gp[r]);
   }
   while (x > r) {
-    int n = ld_ag(&gp[x]);
+    int n = ld_wk(&gp[x]);
     if (n <= r || n == x) break;
     st_ag(&gp[x], r);
     x = n;
@@ -248,7 +259,8 @@ __device__ inline void gunion(int32_t* gp, int a, int b) {
     b = gfind(gp, b);
     if (a == b) return;
     if (a > b) { int t = a; a = b; b = t; }
-    // link the larger root under the smaller one, only if it is still a root
+    // link the larger root under the smaller one, only if it is still a root;
+    // on failure b holds the entry's current value (a strict ancestor)
     if (__hip_atomic_compare_exchange_strong(&gp[b], &b, a, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                              __HIP_MEMORY_SCOPE_AGENT))
       return;
@@ -892,29 +904,17 @@ __global__ void __launch_bounds__(256) k_border_merge(Src src, Work wk, int64_t 
 }
 
 // ---------------------------------------------------------------------------
-// K3: final roots.  k_flatten points every border node at its root;
-// k_reduce_roots then adds the partial features (and minimum key) of every
-// non-root node into its root.  To keep the number of global atomics on the
-// accumulators of components spanning many tiles (the exterior, percolating
-// clusters) small, a workgroup first merges the contributions of a group of
-// consecutive tiles in an LDS hash table keyed by root and issues one set of
-// atomics per root per flush.
+// K3: final roots and class sums.  Every border node is pointed at its root
+// (find with full compression; no unions run any more), and the partial
+// features (and minimum key) of every non-root node are added into its root.
+// To keep the number of global atomics on the accumulators of components
+// spanning many tiles (the exterior, percolating clusters) small, a workgroup
+// first merges the contributions of the nodes of a group of consecutive tiles
+// in an LDS hash table keyed by root and issues one set of atomics per root
+// per flush.
 
-template <class T, class Src>
-__global__ void __launch_bounds__(64) k_flatten(Src src, Work wk) {
-  const int64_t gt = blockIdx.x;
-  const ImgDesc& d = src.by_tile(gt);
-  const int64_t nbase = tile_node_base<T>(d, gt - d.tile0);
-  const int nb = wk.nbt[gt];
-  for (int i = threadIdx.x; i < nb; i += 64) {
-    int node = (int)(nbase + i);
-    int r = gfind(wk.gpar, node);
-    st_ag(&wk.gpar[node], r);
-  }
-}
-
-constexpr int RH_CAP = 1024;     // LDS hash slots
-constexpr int RH_TILES = 16;     // tiles per workgroup
+constexpr int RH_CAP = 512;      // LDS hash slots
+constexpr int RH_TILES = 32;     // tiles per workgroup
 constexpr int RH_T = 256;        // threads
 constexpr int RH_EMPTY = -1;
 
@@ -936,40 +936,58 @@ __device__ inline void rootacc_clear(RootAcc& a) {
 
 template <class T, class Src>
 __global__ void __launch_bounds__(RH_T) k_reduce_roots(Src src, Work wk, int64_t tiles) {
+  static_assert(RH_TILES <= 64, "one wave scans the group");
   __shared__ RootAcc tab[RH_CAP];
+  __shared__ int pre[RH_TILES + 1];
+  __shared__ int64_t tbase[RH_TILES];
   __shared__ int used;
   const int tid = threadIdx.x;
+  const int64_t t0 = (int64_t)blockIdx.x * RH_TILES;
+  const int ntl = tiles - t0 < RH_TILES ? (int)(tiles - t0) : RH_TILES;
   for (int i = tid; i < RH_CAP; i += RH_T) rootacc_clear(tab[i]);
+  if (tid < 64) {  // node counts of the group's tiles -> exclusive prefix
+    int c = 0;
+    if (tid < ntl) {
+      const int64_t gt = t0 + tid;
+      const ImgDesc& d = src.by_tile(gt);
+      c = wk.nbt[gt];
+      tbase[tid] = tile_node_base<T>(d, gt - d.tile0);
+    }
+    int inc = c;
+    for (int dl = 1; dl < 64; dl <<= 1) {
+      int t = __shfl_up(inc, dl, 64);
+      if (tid >= dl) inc += t;
+    }
+    if (tid < RH_TILES) pre[tid] = inc - c;
+    if (tid == RH_TILES - 1) pre[RH_TILES] = inc;
+  }
   if (tid == 0) used = 0;
   __syncthreads();
-  const int64_t t0 = (int64_t)blockIdx.x * RH_TILES;
-  const int64_t t1 = t0 + RH_TILES < tiles ? t0 + RH_TILES : tiles;
-  // nodes of the group, enumerated tile by tile in chunks of RH_T
-  int64_t gt = t0;
-  int base = 0;
-  while (gt < t1) {
-    const ImgDesc& d = src.by_tile(gt);
-    const int nb = wk.nbt[gt];
-    const int64_t nbase = tile_node_base<T>(d, gt - d.tile0);
-    int i = base + tid;
-    if (i < nb) {
-      int node = (int)(nbase + i);
-      int r = wk.gpar[node];
+  const int total = pre[RH_TILES];
+  // the group's nodes as one list, RH_T at a time
+  for (int base = 0; base < total; base += RH_T) {
+    const int i = base + tid;
+    if (i < total) {
+      int k = 0;
+      for (int m = 1; m < RH_TILES; m++) k += pre[m] <= i ? 1 : 0;
+      const int node = (int)(tbase[k] + (i - pre[k]));
+      const Feature f = wk.gacc[node];
+      const int32_t key = wk.gkey[node];
+      const int r = gfind(wk.gpar, node);  // leaves gpar[node] == r
       if (r != node) {
-        uint32_t hsh = ((uint32_t)r * 2654435761u) >> 22;  // 10 bits
+        uint32_t hsh = ((uint32_t)r * 2654435761u) >> 23;  // 9 bits
         int slot = (int)hsh;
         for (;;) {
-          int k = atomicCAS(&tab[slot].key, RH_EMPTY, r);
-          if (k == RH_EMPTY) {
+          int k2 = atomicCAS(&tab[slot].key, RH_EMPTY, r);
+          if (k2 == RH_EMPTY) {
             atomicAdd(&used, 1);
             break;
           }
-          if (k == r) break;
+          if (k2 == r) break;
           slot = (slot + 1) & (RH_CAP - 1);
         }
         RootAcc& a = tab[slot];
-        Feature f = wk.gacc[node];
-        atomicMin(&a.minkey, wk.gkey[node]);
+        atomicMin(&a.minkey, key);
         atomicMin(&a.xmin, f.xmin);
         atomicMax(&a.xmax, f.xmax);
         atomicMin(&a.ymin, f.ymin);
@@ -979,14 +997,11 @@ __global__ void __launch_bounds__(RH_T) k_reduce_roots(Src src, Work wk, int64_t
         atomicAdd(&a.Sy, (u64)f.Sy);
       }
     }
-    base += RH_T;
-    if (base >= nb) {
-      base = 0;
-      gt++;
-    }
     __syncthreads();
-    // flush when another chunk might not fit, and at the end
-    const bool flush = used > RH_CAP - RH_T || gt >= t1;
+    // flush when another chunk might not fit, and at the end; every thread
+    // reads the count before any thread inserts again
+    const bool flush = used > RH_CAP - RH_T || base + RH_T >= total;
+    __syncthreads();
     if (flush) {
       for (int j = tid; j < RH_CAP; j += RH_T) {
         RootAcc& a = tab[j];
@@ -1003,15 +1018,14 @@ __global__ void __launch_bounds__(RH_T) k_reduce_roots(Src src, Work wk, int64_t
         atomicAdd(reinterpret_cast<unsigned long long*>(&g->Sy), (unsigned long long)a.Sy);
         rootacc_clear(a);
       }
-      __syncthreads();
       if (tid == 0) used = 0;
       __syncthreads();
     }
   }
 }
 
-// The same reduction without the LDS table: every non-root node adds its
-// partial directly into its root with global atomics (one wave per tile).
+// The same work without the LDS table: every non-root node adds its partial
+// directly into its root with global atomics (one wave per tile).
 // Cheaper when components rarely span tiles; contended on giant ones.
 template <class T, class Src>
 __global__ void __launch_bounds__(64) k_reduce_direct(Src src, Work wk) {
@@ -1021,7 +1035,7 @@ __global__ void __launch_bounds__(64) k_reduce_direct(Src src, Work wk) {
   const int nb = wk.nbt[gt];
   for (int i = threadIdx.x; i < nb; i += 64) {
     int node = (int)(nbase + i);
-    int r = wk.gpar[node];
+    int r = gfind(wk.gpar, node);  // leaves gpar[node] == r
     if (r == node) continue;
     atomicMin(&wk.gminkey[r], wk.gkey[node]);
     Feature f = wk.gacc[node];
@@ -1597,7 +1611,6 @@ inline void enqueue(Launcher& L, const Src& src, const Work& wk, int64_t tiles, 
                     int64_t nimages) {
   L.launch(k_tile_export<T, Src>, tiles, T::NT, src, wk);
   if (items > 0) L.launch(k_border_merge<T, Src>, (items + 255) / 256, 256, src, wk, items);
-  L.launch(k_flatten<T, Src>, tiles, 64, src, wk);
   if (HASH) L.launch(k_reduce_roots<T, Src>, (tiles + RH_TILES - 1) / RH_TILES, RH_T, src, wk, tiles);
   else L.launch(k_reduce_direct<T, Src>, tiles, 64, src, wk);
   L.launch(k_leaders<T, Src>, tiles, 64, src, wk);

@@ -45,6 +45,8 @@ struct Sched {
   unsigned long long xchg[16][64];
   const void* main_stack_bottom = nullptr;
   size_t main_stack_size = 0;
+  int sched = 0;                 // 0 thread order, 1 reverse, 2 pseudo-random
+  unsigned long long rng = 1;
 } S;
 
 void* fake_main = nullptr;
@@ -102,9 +104,24 @@ void run_block(unsigned block, unsigned nthreads) {
     makecontext(&fb.ctx, fiber_entry, 0);
   }
   const unsigned nwaves = (nthreads + 63) / 64;
+  // order in which runnable fibers run after each barrier release: thread
+  // order, reverse order, or a fresh pseudo-random permutation each pass
+  // (EMU_SCHED = fwd | rev | <seed>), so that code reading shared state right
+  // after a barrier meets other threads that have already gone on
+  std::vector<unsigned> order(nthreads);
+  for (unsigned t = 0; t < nthreads; t++) order[t] = S.sched == 1 ? nthreads - 1 - t : t;
   for (;;) {
     bool ran = false;
-    for (unsigned t = 0; t < nthreads; t++) {
+    if (S.sched >= 2)
+      for (unsigned t = nthreads; t > 1; t--) {
+        S.rng = S.rng * 6364136223846793005ull + 1442695040888963407ull;
+        unsigned k = (unsigned)((S.rng >> 33) % t);
+        unsigned tmp = order[t - 1];
+        order[t - 1] = order[k];
+        order[k] = tmp;
+      }
+    for (unsigned oi = 0; oi < nthreads; oi++) {
+      const unsigned t = order[oi];
       if (S.f[t].state != RUNNABLE) continue;
       S.cur = t;
       ran = true;
@@ -277,6 +294,13 @@ int main(int argc, char** argv) {
   }
   fclose(fi);
   bool batch = strcmp(argv[2], "batch") == 0;
+  if (const char* e = getenv("EMU_SCHED")) {
+    if (strcmp(e, "rev") == 0) S.sched = 1;
+    else if (strcmp(e, "fwd") != 0) {
+      S.sched = 2;
+      S.rng = strtoull(e, nullptr, 10) * 2 + 1;
+    }
+  }
   int cfg = atoi(argv[1]);
   switch (cfg) {
     case 0: run_images<ccl::Tile<32, 128>>(ims, batch); break;

@@ -57,8 +57,11 @@ class EmuResult:
     euler: int
 
 
-def run(images, tile_cfg: int = 0, batch: bool = False, pitch_pad: int = 0):
-    """Label a list of 2-D uint8 arrays with the emulated kernels."""
+def run(images, tile_cfg: int = 0, batch: bool = False, pitch_pad: int = 0, sched: str = "fwd"):
+    """Label a list of 2-D uint8 arrays with the emulated kernels.
+
+    sched: order in which the threads of a workgroup run after a barrier
+    ("fwd", "rev", or a decimal seed for a pseudo-random order)."""
     exe = build()
     with tempfile.TemporaryDirectory() as td:
         fin, fout = os.path.join(td, "in.bin"), os.path.join(td, "out.bin")
@@ -72,7 +75,7 @@ def run(images, tile_cfg: int = 0, batch: bool = False, pitch_pad: int = 0):
                 f.write(struct.pack("<iiq", w, h, pitch))
                 f.write(buf.tobytes())
         env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
-                   UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
+                   UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1", EMU_SCHED=str(sched))
         p = subprocess.run([exe, str(tile_cfg), "batch" if batch else "single", fin, fout],
                            capture_output=True, text=True, env=env)
         if p.returncode != 0:
