@@ -100,6 +100,7 @@ struct Work {
   int32_t* gminkey;  // [nodes] at roots: minimum key of the class
   int32_t* grank;    // [nodes] bits 0-15 rank / interior-before, 16-21 row, 31 leader
   int32_t* rcanon;   // [nodes] at roots: canonical id
+  int32_t* ncanon;   // [nodes] canonical id of the node's component
   Feature* gacc;     // [nodes] partial features; at roots the class sum
   int32_t* nbt;      // [tiles] border nodes per tile
   u16* bidx_top;     // [tiles*TW] border node index of every top-row pixel
@@ -133,8 +134,8 @@ struct Tile {
   static constexpr int NCH = TH * CPR;     // chunks per tile
   static constexpr int BCAP = 2 * (TH + TW);  // >= border pixels >= border nodes
   static constexpr int NT = 256;           // threads per tile workgroup
-  static constexpr int CAPI = 512;         // interior accumulators per pass
-  static_assert(TW % 64 == 0 && TW <= 1024, "tile width");
+  static constexpr int CAPI = 256;         // interior accumulators per pass
+  static_assert(TW % 64 == 0 && TW <= 256, "tile width (a row rank fits 8 bits)");
   static_assert(TH >= 1 && TH <= 64, "tile height");
   static_assert(N < 65536, "positions must fit 16 bits");
   static_assert((long long)N * (TW - 1) < (1ll << 24), "packed Sx field");
@@ -157,6 +158,13 @@ __device__ inline u64 valid_mask(int j, int width) {  // bits x of word j with 6
 __device__ inline u32 nz4(u32 d) {
   u32 t = (((d & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | d) & 0x80808080u;
   return ((t >> 7) * 0x10204080u) >> 28;
+}
+
+// sum over the 64 lanes of a wave (every lane gets it)
+__device__ inline int wave_sum(int v) {
+  const int lane = (int)(threadIdx.x & 63u);
+  for (int dl = 32; dl >= 1; dl >>= 1) v += __shfl(v, lane ^ dl, 64);
+  return v;
 }
 
 __device__ inline u32 ld_wg(const u32* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
@@ -351,35 +359,84 @@ __device__ inline int iord_of(const TileSmem<T>& s, int r) {  // r: interior roo
   return s.ipre[wd] + popc64(~s.bflag[wd] & s.rootm[wd] & low_mask(r & 63));
 }
 
-// Phases 1-5: load + pack + runs, unite, flatten, border flags and roots,
-// prefix counts.  Returns 1 + colour for a one-colour tile (nothing else is
-// computed then), else 0.  Ends with a barrier; afterwards par[p] is the root
-// position of every run start p, bflag/rootm/bpre/ipre/spre/nb/nint/nruns
-// are valid.
+// Geometry of one tile of an image.
+struct TileGeom {
+  int64_t lt;      // tile index inside its image
+  int tx, ty;      // tile column / row
+  int x0, y0;      // first pixel
+  int tw, th;      // pixels inside the image
+};
 template <class T>
-__device__ int tile_label(TileSmem<T>& s, const u8* img, int64_t pitch, int x0, int y0, int tw, int th,
-                          bool vec_in) {
+__device__ inline TileGeom tile_geom(const ImgDesc& d, int64_t gt) {
+  TileGeom g;
+  g.lt = gt - d.tile0;
+  g.tx = (int)(g.lt % d.ntx);
+  g.ty = (int)(g.lt / d.ntx);
+  g.x0 = g.tx * T::TW;
+  g.y0 = g.ty * T::TH;
+  g.tw = d.w - g.x0 < T::TW ? d.w - g.x0 : T::TW;
+  g.th = d.h - g.y0 < T::TH ? d.h - g.y0 : T::TH;
+  return g;
+}
+
+// Image bytes of one thread's 16-pixel chunks (and the byte before the chunk
+// for a wave's first lane), all requested before any is used.  Chunks that
+// are not whole 16-byte aligned vectors are read at use.
+template <class T>
+struct TileFetch {
+  static constexpr int K = (T::NCH + T::NT - 1) / T::NT;
+  uint4 v[K];
+  u32 prevb[K];
+};
+
+template <class T>
+__device__ inline void tile_fetch(TileFetch<T>& f, const ImgDesc& d, const TileGeom& g) {
+  const int tid = threadIdx.x;
+  const bool vec_in = (d.flags & DF_VEC_IN) != 0;
+#pragma unroll
+  for (int k = 0; k < TileFetch<T>::K; k++) {
+    const int c = k * T::NT + tid;
+    const int ly = c / T::CPR, cx = (c % T::CPR) * 16;
+    const bool in = c < T::NCH && ly < g.th && cx < g.tw;
+    const u8* src = d.img + (int64_t)(g.y0 + ly) * d.pitch + (g.x0 + cx);
+    uint4 v;
+    v.x = v.y = v.z = v.w = 0u;
+    if (in && vec_in && cx + 16 <= g.tw) v = *reinterpret_cast<const uint4*>(src);
+    f.v[k] = v;
+    f.prevb[k] = in && cx > 0 && (tid & 63) == 0 ? (u32)src[-1] : 0u;
+  }
+}
+
+// Phase 1: pack + runs.  Returns 1 + colour for a one-colour tile, else 0.
+// Ends with a barrier; afterwards bits/st are valid and par[p] == p at every
+// run start p (general tile).
+template <class T>
+__device__ int tile_pack(TileSmem<T>& s, const TileFetch<T>& f, const ImgDesc& d, const TileGeom& g) {
   static_assert(T::NCH % 64 == 0 || T::NCH < 64, "whole waves per chunk loop");
   const int tid = threadIdx.x;
-  // 1. load bytes, 16 pixels per chunk -> 16 bits; run starts (the pixel
-  // before the chunk comes from the lane holding the previous chunk, or from
-  // memory at a wave's first lane); par[p] = p at every run start; vote on a
-  // one-colour tile
+  const int tw = g.tw, th = g.th;
+  const bool vec_in = (d.flags & DF_VEC_IN) != 0;
+  // 1. bytes -> 16 bits per chunk; run starts (the pixel before the chunk
+  // comes from the lane holding the previous chunk, or from memory at a
+  // wave's first lane); par[p] = p at every run start; vote on a one-colour
+  // tile
   bool all0 = true, all1 = true;
-  for (int c0 = 0; c0 < T::NCH; c0 += T::NT) {
+#pragma unroll
+  for (int k = 0; k < TileFetch<T>::K; k++) {
+    const int c0 = k * T::NT;
     const int c = c0 + tid;
     if (c0 + (tid & ~63) >= T::NCH) break;  // whole waves leave together
     const int ly = c / T::CPR, cc = c % T::CPR, cx = cc * 16;
     const bool in = c < T::NCH && ly < th && cx < tw;
     u32 m = 0;
-    const u8* src = img + (int64_t)(y0 + ly) * pitch + (x0 + cx);
     if (in) {
       if (vec_in && cx + 16 <= tw) {
-        uint4 v = *reinterpret_cast<const uint4*>(src);
+        const uint4 v = f.v[k];
         m = nz4(v.x) | (nz4(v.y) << 4) | (nz4(v.z) << 8) | (nz4(v.w) << 12);
       } else {
+        const u8* src = d.img + (int64_t)(g.y0 + ly) * d.pitch + (g.x0 + cx);
         int n = tw - cx < 16 ? tw - cx : 16;
-        for (int k = 0; k < n; k++) m |= (u32)(src[k] != 0) << k;
+        for (int q = 0; q < n; q++) m |= (u32)(src[q] != 0) << q;
       }
     }
     u32 prev = __shfl_up(m, 1, 64);
@@ -389,7 +446,7 @@ __device__ int tile_label(TileSmem<T>& s, const u8* img, int64_t pitch, int x0, 
     if (in) {
       u32 carry;
       if (cc == 0) carry = ~m & 1u;
-      else if ((tid & 63) == 0) carry = src[-1] != 0;
+      else if ((tid & 63) == 0) carry = f.prevb[k] != 0u;
       else carry = prev >> 15;
       const u32 vm = (u32)valid_mask(0, tw - cx) & 0xFFFFu;
       e = (m ^ ((m << 1) | carry)) & vm;
@@ -403,7 +460,16 @@ __device__ int tile_label(TileSmem<T>& s, const u8* img, int64_t pitch, int x0, 
   for (int i = tid; i < T::NW; i += T::NT) s.bflag[i] = 0;
   const int u0 = __syncthreads_and(all0);
   const int u1 = __syncthreads_and(all1);
-  if (u0 || u1) return u1 ? 2 : 1;
+  return u0 || u1 ? (u1 ? 2 : 1) : 0;
+}
+
+// Phases 2-5 of a general tile: unite, flatten, border flags and roots,
+// prefix counts.  Ends with a barrier; afterwards par[p] is the root
+// position of every run start p, bflag/rootm/bpre/ipre/spre/nb/nint/nruns
+// are valid.
+template <class T>
+__device__ void tile_unite(TileSmem<T>& s, int tw, int th) {
+  const int tid = threadIdx.x;
 
   // 2. unite runs of rows ly-1, ly (all row pairs at once)
   for (int c = tid; c < T::NCH; c += T::NT) {
@@ -521,7 +587,6 @@ __device__ int tile_label(TileSmem<T>& s, const u8* img, int64_t pitch, int x0, 
     }
   }
   __syncthreads();
-  return 0;
 }
 
 // Segments of one 16-pixel chunk: calls f(run_start_x, seg_begin, seg_end).
@@ -550,12 +615,33 @@ __device__ inline void acc_init(Acc& a) {
   a.xmax = 0;
   a.ymax = 0;
 }
-__device__ inline void acc_add(Acc& a, int ly, int s0, int e0) {
-  atomicAdd(&a.s, seg_pack(ly, s0, e0));
-  atomicMin(&a.xmin, (u32)s0);
-  atomicMax(&a.xmax, (u32)(e0 - 1));
+// Segments of one row summed in registers before they go to a shared
+// accumulator: consecutive segments (in x order) of one component.
+struct RowSum {
+  int o;       // accumulator index, -1: none
+  u64 s;       // packed S | Sx | Sy
+  u32 xmin, xmax;
+};
+__device__ inline void rowsum_flush(RowSum& r, Acc* acc, int ly) {
+  if (r.o < 0) return;
+  Acc& a = acc[r.o];
+  atomicAdd(&a.s, r.s);
+  atomicMin(&a.xmin, r.xmin);
+  atomicMax(&a.xmax, r.xmax);
   atomicMax(&a.ymax, (u32)ly);
+  r.o = -1;
 }
+__device__ inline void rowsum_add(RowSum& r, Acc* acc, int o, int ly, int s0, int e0) {
+  if (o != r.o) {
+    rowsum_flush(r, acc, ly);
+    r.o = o;
+    r.s = 0;
+    r.xmin = (u32)s0;
+  }
+  r.s += seg_pack(ly, s0, e0);
+  r.xmax = (u32)(e0 - 1);
+}
+
 __device__ inline Feature acc_abs(const Acc& a, int ly_min, int x0, int y0) {
   Feature f;
   int64_t S = (int64_t)(a.s & 0xFFFFull);
@@ -612,17 +698,13 @@ __device__ inline int64_t tile_node_base(const ImgDesc& d, int64_t lt) {  // slo
 // ---------------------------------------------------------------------------
 // K1: tile labeling and export of border nodes
 
-template <class T, class Src>
-__global__ void __launch_bounds__(256) k_tile_export(Src src, Work wk) {
-  __shared__ TileSmem<T> s;
-  __shared__ Acc bacc[T::BCAP];
-  const int64_t gt = blockIdx.x;
-  const ImgDesc& d = src.by_tile(gt);
-  const int64_t lt = gt - d.tile0;
-  const int tx = (int)(lt % d.ntx), ty = (int)(lt / d.ntx);
-  const int x0 = tx * T::TW, y0 = ty * T::TH;
-  const int tw = d.w - x0 < T::TW ? d.w - x0 : T::TW;
-  const int th = d.h - y0 < T::TH ? d.h - y0 : T::TH;
+// One tile after phase 1 (uni: tile_pack's result).
+template <class T>
+__device__ void export_tile(TileSmem<T>& s, Acc* bacc, const ImgDesc& d, const TileGeom& g, int64_t gt, int uni,
+                            const Work& wk) {
+  const int64_t lt = g.lt;
+  const int tx = g.tx;
+  const int x0 = g.x0, y0 = g.y0, tw = g.tw, th = g.th;
   const int tid = threadIdx.x;
 
   if (lt == 0 && tid == 0) {  // per-image state read by later kernels
@@ -636,7 +718,6 @@ __global__ void __launch_bounds__(256) k_tile_export(Src src, Work wk) {
     if (d.counts) d.counts[1] = 0;
   }
 
-  const int uni = tile_label<T>(s, d.img, d.pitch, x0, y0, tw, th, (d.flags & DF_VEC_IN) != 0);
   const int64_t nbase = tile_node_base<T>(d, lt);
 
   if (uni) {
@@ -679,6 +760,8 @@ __global__ void __launch_bounds__(256) k_tile_export(Src src, Work wk) {
     }
     return;
   }
+
+  tile_unite<T>(s, tw, th);
 
   // 6. root ordinal of every run start (border roots first, then interior
   // roots) into par and into the tile state for K6; border node records;
@@ -734,10 +817,13 @@ __global__ void __launch_bounds__(256) k_tile_export(Src src, Work wk) {
   for (int c = tid; c < T::NCH; c += T::NT) {
     int ly = c / T::CPR, cc = c % T::CPR;
     if (ly >= th) continue;
+    RowSum rs;
+    rs.o = -1;
     for_segments<T>(s, ly, cc, tw, [&](int start, int a, int b) {
       int o = s.par[ly * T::TW + start];
-      if (o < nb) acc_add(bacc[o], ly, a, b);
+      if (o < nb) rowsum_add(rs, bacc, o, ly, a, b);
     });
+    rowsum_flush(rs, bacc, ly);
   }
   __syncthreads();
 
@@ -780,6 +866,19 @@ __global__ void __launch_bounds__(256) k_tile_export(Src src, Work wk) {
       wk.bits_lr[gt * 2 + right] = col;
     }
   }
+}
+
+template <class T, class Src>
+__global__ void __launch_bounds__(256) k_tile_export(Src src, Work wk) {
+  __shared__ TileSmem<T> s;
+  __shared__ Acc bacc[T::BCAP];
+  const int64_t gt = blockIdx.x;
+  const ImgDesc& d = src.by_tile(gt);
+  const TileGeom g = tile_geom<T>(d, gt);
+  TileFetch<T> f;
+  tile_fetch<T>(f, d, g);
+  const int uni = tile_pack<T>(s, f, d, g);
+  export_tile<T>(s, bacc, d, g, gt, uni, wk);
 }
 
 // ---------------------------------------------------------------------------
@@ -1210,6 +1309,21 @@ __global__ void __launch_bounds__(64) k_emit_border(Src src, Work wk) {
   }
 }
 
+// K5b: the canonical id of every border node (its root's), so that K6 reads
+// it in one step.  One thread per node slot.
+
+template <class T, class Src>
+__global__ void __launch_bounds__(256) k_node_canon(Src src, Work wk, int64_t slots) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= slots) return;
+  const int64_t gt = i / T::BCAP;
+  const int k = (int)(i % T::BCAP);
+  if (k >= wk.nbt[gt]) return;
+  const ImgDesc& d = src.by_tile(gt);
+  const int node = (int)(tile_node_base<T>(d, gt - d.tile0) + k);
+  wk.ncanon[node] = wk.rcanon[wk.gpar[node]];
+}
+
 // ---------------------------------------------------------------------------
 // K6: relabel the tile, write labels and the tables of the components it
 // owns.  Works from the tile state K1 left (no image reload, no union-find).
@@ -1224,11 +1338,26 @@ struct EmitSmem {
   u16 spre[T::NW];     // run starts before word (tile raster order)
   u16 bpre[T::NW];     // border roots before word
   u16 ipre[T::NW];     // interior roots before word
-  u16 ordr[T::N];      // root ordinal by run rank
-  int32_t canon[T::N]; // canonical id by root ordinal
+  union {
+    struct {
+      u16 ordr[T::N];    // root ordinal by run rank
+      u16 icanon[T::N];  // interior root nb + i: row << 8 | rank among the row's leaders
+    } o;
+    int32_t rcan[T::N];  // finally: canonical id by run rank
+  } rt;
+  int32_t bcanon[T::BCAP];  // canonical id of border root ordinal o (o < nb)
   int32_t rowbase[T::TH];  // first canonical id of the row's components starting here
+  int32_t lcanon[T::TH];   // canonical id of the pixel left of the tile, per row
   int nb, nint, nruns, euler;
 };
+
+// canonical id of root ordinal o
+template <class T>
+__device__ inline int32_t canon_of(const EmitSmem<T>& s, int o) {
+  if (o < s.nb) return s.bcanon[o];
+  const u32 v = s.rt.o.icanon[o - s.nb];
+  return s.rowbase[v >> 8] + (int32_t)(v & 0xFFu);
+}
 
 template <class T>
 __device__ inline int run_rank(const EmitSmem<T>& s, int ly, int x) {  // run holding pixel (ly, x)
@@ -1269,18 +1398,31 @@ __global__ void __launch_bounds__(256) k_tile_emit(Src src, Work wk) {
   const int th = d.h - y0 < T::TH ? d.h - y0 : T::TH;
   const int tid = threadIdx.x;
   const int64_t nbase = tile_node_base<T>(d, lt);
+  // everything that does not depend on the tile kind is requested at once
   const int info = wk.tinfo[gt];
+  const int nbt = wk.nbt[gt];
+  const int32_t canon0 = wk.ncanon[nbase];
+  const int grank0 = wk.grank[nbase];
+  const u64* ts = wk.tstate + gt * 3 * T::NW;
+  u64 tsv[(3 * T::NW + T::NT - 1) / T::NT];
+#pragma unroll
+  for (int k = 0; k < (3 * T::NW + T::NT - 1) / T::NT; k++) {
+    int i = tid + k * T::NT;
+    tsv[k] = i < 3 * T::NW ? ts[i] : 0ull;
+  }
+  const int32_t rowb = tid < th ? wk.cgrid[d.c0 + (int64_t)(y0 + tid) * d.ntx + tx] : 0;
+  // node of the left neighbour's right column, per row (parents of
+  // components whose first pixel is in column 0)
+  const int lnode = tid < th && tx > 0 ? col_node<T>(wk, d, tx - 1, y0 + tid, true) : -1;
 
   if (info & 3) {
     // one-colour tile: its single component is border node slot 0
     const int col = (info & 3) - 1;
-    const int node = (int)nbase;
-    const int32_t canon = wk.rcanon[wk.gpar[node]];
-    if (tid == 0 && (wk.grank[node] & (int)HI)) {  // the component starts here
+    const int32_t canon = canon0;
+    if (tid == 0 && (grank0 & (int)HI)) {  // the component starts here
       if (canon < d.cap) {
         if (d.color) d.color[canon] = (u8)col;
-        if (d.parent)
-          d.parent[canon] = tx > 0 ? wk.rcanon[wk.gpar[col_node<T>(wk, d, tx - 1, y0, true)]] : 0;
+        if (d.parent) d.parent[canon] = tx > 0 ? wk.ncanon[col_node<T>(wk, d, tx - 1, y0, true)] : 0;
       }
       if (d.counts)
         atomicAdd(reinterpret_cast<unsigned long long*>(&d.counts[1]), (unsigned long long)(int64_t)(col ? 1 : -1));
@@ -1307,23 +1449,23 @@ __global__ void __launch_bounds__(256) k_tile_emit(Src src, Work wk) {
   // 1. tile state, root ordinals of the runs, row bases; canonical ids of the
   // border roots (HI marks the ones holding their component's first pixel)
   const int nruns = info >> 2;
-  const int nbt = wk.nbt[gt];
-  const u64* ts = wk.tstate + gt * 3 * T::NW;
-  for (int i = tid; i < 3 * T::NW; i += T::NT) {
-    u64 v = ts[i];
-    int k = i / T::NW, wd = i % T::NW;
-    if (k == 0) s.bits[wd] = v;
-    else if (k == 1) s.rootm[wd] = v;
-    else s.broot[wd] = v;
+#pragma unroll
+  for (int k = 0; k < (3 * T::NW + T::NT - 1) / T::NT; k++) {
+    int i = tid + k * T::NT;
+    if (i < 3 * T::NW) {
+      int kk = i / T::NW, wd = i % T::NW;
+      if (kk == 0) s.bits[wd] = tsv[k];
+      else if (kk == 1) s.rootm[wd] = tsv[k];
+      else s.broot[wd] = tsv[k];
+    }
   }
   const u16* to = wk.tord + gt * T::N;
-  for (int r = tid; r < nruns; r += T::NT) s.ordr[r] = to[r];
-  for (int ly = tid; ly < th; ly += T::NT) s.rowbase[ly] = wk.cgrid[d.c0 + (int64_t)(y0 + ly) * d.ntx + tx];
-  for (int bi = tid; bi < nbt; bi += T::NT) {
-    int node = (int)(nbase + bi);
-    int g = wk.grank[node];
-    s.canon[bi] = wk.rcanon[wk.gpar[node]] | (g & (int)HI);
+  for (int r = tid; r < nruns; r += T::NT) s.rt.o.ordr[r] = to[r];
+  if (tid < th) {
+    s.rowbase[tid] = rowb;
+    s.lcanon[tid] = lnode >= 0 ? wk.ncanon[lnode] : 0;
   }
+  for (int bi = tid; bi < nbt; bi += T::NT) s.bcanon[bi] = wk.ncanon[nbase + bi] | (wk.grank[nbase + bi] & (int)HI);
   if (tid == 0) s.euler = 0;
   __syncthreads();
 
@@ -1385,10 +1527,10 @@ __global__ void __launch_bounds__(256) k_tile_emit(Src src, Work wk) {
     for (u32 m = (u32)(bmw >> sh) & 0xFFFFu; m; m &= m - 1) {
       int k = ctz32(m);
       int bi = s.bpre[wd] + popc64(bmw & low_mask(sh + k));
-      int32_t cv = s.canon[bi];
+      int32_t cv = s.bcanon[bi];
       if (cv & (int32_t)HI) {
         lead |= 1u << k;
-        s.canon[bi] = cv & ~(int32_t)HI;
+        s.bcanon[bi] = cv & ~(int32_t)HI;
       }
     }
     if (lead) reinterpret_cast<u16*>(s.lmask)[c] |= (u16)lead;
@@ -1411,14 +1553,14 @@ __global__ void __launch_bounds__(256) k_tile_emit(Src src, Work wk) {
     if (!im) continue;
     int rowlead = popc64(s.lmask[wd] & low_mask(sh));
     for (int jj = 0; jj < j; jj++) rowlead += popc64(s.lmask[ly * T::WPR + jj]);
-    const int32_t base = s.rowbase[ly] + rowlead;
     for (; im; im &= im - 1) {
       int k = ctz32(im);
       int ii = s.ipre[wd] + popc64(imw & low_mask(sh + k));
-      s.canon[nb + ii] = base + popc64(lm & ((1u << k) - 1u));
+      s.rt.o.icanon[ii] = (u16)((ly << 8) | (rowlead + popc64(lm & ((1u << k) - 1u))));
     }
   }
-  atomicAdd(&s.euler, e_local);
+  e_local = wave_sum(e_local);
+  if ((tid & 63) == 0 && e_local) atomicAdd(&s.euler, e_local);
   __syncthreads();
   if (tid == 0 && s.euler != 0 && d.counts)
     atomicAdd(reinterpret_cast<unsigned long long*>(&d.counts[1]), (unsigned long long)(int64_t)s.euler);
@@ -1431,10 +1573,13 @@ __global__ void __launch_bounds__(256) k_tile_emit(Src src, Work wk) {
     for (int c = tid; c < T::NCH; c += T::NT) {
       int ly = c / T::CPR, cc = c % T::CPR;
       if (ly >= th) continue;
+      RowSum rs;
+      rs.o = -1;
       for_runs<T>(s, ly, cc, tw, [&](int rank, int a, int b) {
-        int o = (int)s.ordr[rank] - nb - k0;
-        if (o >= 0 && o < T::CAPI) acc_add(iacc[o], ly, a, b);
+        int o = (int)s.rt.o.ordr[rank] - nb - k0;
+        if (o >= 0 && o < T::CAPI) rowsum_add(rs, iacc, o, ly, a, b);
       });
+      rowsum_flush(rs, iacc, ly);
     }
     __syncthreads();
     for (int c = tid; c < T::NCH; c += T::NT) {
@@ -1447,17 +1592,36 @@ __global__ void __launch_bounds__(256) k_tile_emit(Src src, Work wk) {
         int ii = s.ipre[wd] + popc64(imw & low_mask(k));
         int o = ii - k0;
         if (o < 0 || o >= T::CAPI) continue;
-        int32_t canon = s.canon[nb + ii];
+        int32_t canon = canon_of(s, nb + ii);
         if (canon >= d.cap) continue;
         if (d.feat) d.feat[canon] = acc_abs(iacc[o], ly, x0, y0);
         if (d.color) d.color[canon] = (u8)((s.bits[wd] >> k) & 1ull);
-        if (d.parent) d.parent[canon] = s.canon[s.ordr[run_rank(s, ly, j * 64 + k - 1)]];  // interior: x > 0
+        if (d.parent) d.parent[canon] = canon_of(s, s.rt.o.ordr[run_rank(s, ly, j * 64 + k - 1)]);  // interior: x > 0
       }
     }
     __syncthreads();
   }
 
-  // 7. colour / parent of border components whose first pixel is here
+  // 7. canonical id of every run, in place of the ordinals (values pass
+  // through registers: the two tables overlap)
+  {
+    constexpr int RPT = (T::N + T::NT - 1) / T::NT;
+    int32_t rc[RPT];
+#pragma unroll
+    for (int k = 0; k < RPT; k++) {
+      const int r = tid + k * T::NT;
+      rc[k] = r < nruns ? canon_of(s, s.rt.o.ordr[r]) : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < RPT; k++) {
+      const int r = tid + k * T::NT;
+      if (r < nruns) s.rt.rcan[r] = rc[k];
+    }
+    __syncthreads();
+  }
+
+  // 8. colour / parent of border components whose first pixel is here
   for (int c = tid; c < T::NCH; c += T::NT) {
     int ly = c / T::CPR, cc = c % T::CPR;
     int j = cc >> 2, sh = (cc & 3) * 16;
@@ -1465,35 +1629,35 @@ __global__ void __launch_bounds__(256) k_tile_emit(Src src, Work wk) {
     const u64 bmw = s.broot[wd];
     for (u32 bl = (u32)((bmw & s.lmask[wd]) >> sh) & 0xFFFFu; bl; bl &= bl - 1) {
       int k = sh + ctz32(bl);
-      int32_t canon = s.canon[s.bpre[wd] + popc64(bmw & low_mask(k))];
+      int32_t canon = s.bcanon[s.bpre[wd] + popc64(bmw & low_mask(k))];
       if (canon >= d.cap) continue;
       if (d.color) d.color[canon] = (u8)((s.bits[wd] >> k) & 1ull);
       if (d.parent) {
         int x = j * 64 + k;
         int32_t pc;
-        if (x > 0) pc = s.canon[s.ordr[run_rank(s, ly, x - 1)]];
-        else if (tx > 0) pc = wk.rcanon[wk.gpar[col_node<T>(wk, d, tx - 1, y0 + ly, true)]];
-        else pc = 0;
+        if (x > 0) pc = s.rt.rcan[run_rank(s, ly, x - 1)];
+        else pc = s.lcanon[ly];  // 0 (exterior) at the image's left edge
         d.parent[canon] = pc;
       }
     }
   }
 
-  // 8. label image, four pixels per thread
+  // 9. label image, four pixels per thread
   if (d.labels) {
     const bool vec = (d.flags & DF_VEC_LAB) != 0;
     for (int q = tid; q < T::TH * (T::TW / 4); q += T::NT) {
       int ly = q / (T::TW / 4), x = (q % (T::TW / 4)) * 4;
       if (ly >= th || x >= tw) continue;
-      int r = run_rank(s, ly, x);
+      const int r0 = run_rank(s, ly, x);
+      const u32 sw = (u32)(s.st[ly * T::WPR + (x >> 6)] >> (x & 63));
+      const int r1 = r0 + (int)((sw >> 1) & 1u);
+      const int r2 = r1 + (int)((sw >> 2) & 1u);
+      const int r3 = r2 + (int)((sw >> 3) & 1u);
       int32_t lab[4];
-      int32_t cur = s.canon[s.ordr[r]];
-      u64 sw = s.st[ly * T::WPR + (x >> 6)] >> (x & 63);
-      lab[0] = cur;
-      for (int k = 1; k < 4; k++) {
-        if ((sw >> k) & 1ull) cur = s.canon[s.ordr[++r]];
-        lab[k] = cur;
-      }
+      lab[0] = s.rt.rcan[r0];
+      lab[1] = s.rt.rcan[r1];
+      lab[2] = s.rt.rcan[r2];
+      lab[3] = s.rt.rcan[r3];
       int32_t* dst = d.labels + (int64_t)(y0 + ly) * d.w + x0 + x;
       if (vec && x + 4 <= tw) {
         int4 v4;
@@ -1512,7 +1676,7 @@ __global__ void __launch_bounds__(256) k_tile_emit(Src src, Work wk) {
 
 struct Layout {
   int64_t tiles, nodes, cells, blocks;
-  size_t off_gpar, off_gkey, off_gminkey, off_grank, off_rcanon, off_gacc, off_nbt;
+  size_t off_gpar, off_gkey, off_gminkey, off_grank, off_rcanon, off_ncanon, off_gacc, off_nbt;
   size_t off_btop, off_bbot, off_bleft, off_bright, off_bitstop, off_bitsbot, off_bitslr;
   size_t off_cgrid, off_bsum, off_tinfo, off_tstate, off_tord, bytes;
 };
@@ -1537,6 +1701,7 @@ inline Layout make_layout(int64_t tiles, int64_t nodes, int64_t cells, int64_t b
   L.off_gminkey = take(4 * (size_t)nodes);
   L.off_grank = take(4 * (size_t)nodes);
   L.off_rcanon = take(4 * (size_t)nodes);
+  L.off_ncanon = take(4 * (size_t)nodes);
   L.off_gacc = take(sizeof(Feature) * (size_t)nodes);
   L.off_nbt = take(4 * (size_t)tiles);
   L.off_btop = take(2 * (size_t)tiles * T::TW);
@@ -1563,6 +1728,7 @@ inline Work make_work(const Layout& L, void* ws) {
   w.gminkey = reinterpret_cast<int32_t*>(b + L.off_gminkey);
   w.grank = reinterpret_cast<int32_t*>(b + L.off_grank);
   w.rcanon = reinterpret_cast<int32_t*>(b + L.off_rcanon);
+  w.ncanon = reinterpret_cast<int32_t*>(b + L.off_ncanon);
   w.gacc = reinterpret_cast<Feature*>(b + L.off_gacc);
   w.nbt = reinterpret_cast<int32_t*>(b + L.off_nbt);
   w.bidx_top = reinterpret_cast<u16*>(b + L.off_btop);
@@ -1618,6 +1784,7 @@ inline void enqueue(Launcher& L, const Src& src, const Work& wk, int64_t tiles, 
   L.launch(k_scan_blocks<Src>, nimages, SCAN_T, src, wk);
   L.launch(k_scan_apply<Src>, blocks, SCAN_T, src, wk);
   L.launch(k_emit_border<T, Src>, tiles, 64, src, wk);
+  L.launch(k_node_canon<T, Src>, (tiles * T::BCAP + 255) / 256, 256, src, wk, tiles * T::BCAP);
   L.launch(k_tile_emit<T, Src>, tiles, T::NT, src, wk);
 }
 
