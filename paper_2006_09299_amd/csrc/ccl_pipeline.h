@@ -1414,6 +1414,12 @@ __global__ void __launch_bounds__(256) k_tile_emit(Src src, Work wk) {
   // node of the left neighbour's right column, per row (parents of
   // components whose first pixel is in column 0)
   const int lnode = tid < th && tx > 0 ? col_node<T>(wk, d, tx - 1, y0 + tid, true) : -1;
+  // also, before the tile's kind is known: the first 2 NT run ordinals and
+  // the first NT border nodes (entries past the tile's counts are unused)
+  const u32 ord2 = reinterpret_cast<const u32*>(wk.tord + gt * T::N)[tid < T::N / 2 ? tid : 0];
+  const int bslot = tid < T::BCAP ? tid : 0;
+  const int32_t bcan = wk.ncanon[nbase + bslot];
+  const int bgr = wk.grank[nbase + bslot];
 
   if (info & 3) {
     // one-colour tile: its single component is border node slot 0
@@ -1460,14 +1466,18 @@ __global__ void __launch_bounds__(256) k_tile_emit(Src src, Work wk) {
     }
   }
   const u16* to = wk.tord + gt * T::N;
-  for (int r = tid; r < nruns; r += T::NT) s.rt.o.ordr[r] = to[r];
-  if (tid < th) {
-    s.rowbase[tid] = rowb;
-    s.lcanon[tid] = lnode >= 0 ? wk.ncanon[lnode] : 0;
+  if (2 * tid < nruns && tid < T::N / 2) {
+    s.rt.o.ordr[2 * tid] = (u16)(ord2 & 0xFFFFu);
+    if (2 * tid + 1 < nruns) s.rt.o.ordr[2 * tid + 1] = (u16)(ord2 >> 16);
   }
-  for (int bi = tid; bi < nbt; bi += T::NT) s.bcanon[bi] = wk.ncanon[nbase + bi] | (wk.grank[nbase + bi] & (int)HI);
+  for (int r = 2 * T::NT + tid; r < nruns; r += T::NT) s.rt.o.ordr[r] = to[r];
+  if (tid < th) s.rowbase[tid] = rowb;
+  if (tid < nbt && tid < T::BCAP) s.bcanon[tid] = bcan | (bgr & (int)HI);
+  for (int bi = T::NT + tid; bi < nbt; bi += T::NT) s.bcanon[bi] = wk.ncanon[nbase + bi] | (wk.grank[nbase + bi] & (int)HI);
   if (tid == 0) s.euler = 0;
   __syncthreads();
+  // the left neighbour's canonical ids are first used in step 8
+  const int32_t lcv = lnode >= 0 ? wk.ncanon[lnode] : 0;
 
   // 2. run starts; interior roots lead
   for (int wd = tid; wd < T::NW; wd += T::NT) {
@@ -1618,6 +1628,7 @@ __global__ void __launch_bounds__(256) k_tile_emit(Src src, Work wk) {
       const int r = tid + k * T::NT;
       if (r < nruns) s.rt.rcan[r] = rc[k];
     }
+    if (tid < th) s.lcanon[tid] = lcv;
     __syncthreads();
   }
 
