@@ -160,6 +160,13 @@ __device__ inline u32 nz4(u32 d) {
   return ((t >> 7) * 0x10204080u) >> 28;
 }
 
+// LDS written by some lanes of a wave is read by others after this point
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  (void)__ballot(1);
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // sum over the 64 lanes of a wave (every lane gets it)
 __device__ inline int wave_sum(int v) {
   const int lane = (int)(threadIdx.x & 63u);
@@ -468,32 +475,62 @@ __device__ int tile_pack(TileSmem<T>& s, const TileFetch<T>& f, const ImgDesc& d
 // position of every run start p, bflag/rootm/bpre/ipre/spre/nb/nint/nruns
 // are valid.
 template <class T>
-__device__ void tile_unite(TileSmem<T>& s, int tw, int th) {
+__device__ void tile_unite(TileSmem<T>& s, u32* stage_all, int stage_words, int tw, int th) {
   const int tid = threadIdx.x;
+  const int lane = tid & 63;
 
-  // 2. unite runs of rows ly-1, ly (all row pairs at once)
-  for (int c = tid; c < T::NCH; c += T::NT) {
-    int ly = c / T::CPR, cc = c % T::CPR;
-    if (ly == 0 || ly >= th || cc * 16 >= tw) continue;
-    int j = cc >> 2, sh = (cc & 3) * 16;
-    const u64* B0 = &s.bits[ly * T::WPR];
-    const u64* B1 = &s.bits[(ly - 1) * T::WPR];
-    u64 m0 = B0[j], m1 = B1[j];
-    u64 m0p = j ? B0[j - 1] : 0ull, m1p = j ? B1[j - 1] : 0ull;
-    u64 m0n = j + 1 < T::WPR ? B0[j + 1] : 0ull, m1n = j + 1 < T::WPR ? B1[j + 1] : 0ull;
-    PairMasks pm = pair_masks(m0, m1, m0p, m1p, m0n, m1n, valid_mask(j, tw), j > 0);
-    // one loop over all union points of the chunk: bits 0-15 vertical,
-    // 16-31 diagonal up-right, 32-47 diagonal up-left
-    u64 pts = ((pm.vert >> sh) & 0xFFFFull) | (((pm.da >> sh) & 0xFFFFull) << 16) |
-              (((pm.db >> sh) & 0xFFFFull) << 32);
-    const u32 r0 = (u32)(ly * T::TW), r1 = (u32)((ly - 1) * T::TW);
-    const int xb = j * 64 + sh;
-    while (pts) {
-      const int k = __builtin_ctzll(pts);
-      pts &= pts - 1;
-      const int x = xb + (k & 15);
-      const int xu = x + (k >> 4 == 1) - (k >> 4 == 2);
-      lunion(s.par, r0 + run_start(s, ly, x), r1 + run_start(s, ly - 1, xu));
+  // 2. unite runs of rows ly-1, ly (all row pairs at once).  Each lane finds
+  // the union points of one 16-pixel chunk; the wave then lists them in LDS
+  // (x | row << 10 | kind << 16) and works through the list 64 at a time, so
+  // that its iterations follow the wave's total instead of its busiest lane.
+  const int scap = stage_words / (T::NT / 64);
+  u32* stage = stage_all + (tid >> 6) * scap;
+#pragma unroll
+  for (int k = 0; k < (T::NCH + T::NT - 1) / T::NT; k++) {
+    if (k * T::NT + (tid & ~63) >= T::NCH) break;  // whole waves leave together
+    const int c = k * T::NT + tid;
+    const int ly = c / T::CPR, cc = c % T::CPR;
+    // bits 0-15: vertical; 16-31: diagonal up-right; 32-47: diagonal up-left
+    u64 pts = 0;
+    int xb = 0;
+    if (c < T::NCH && ly > 0 && ly < th && cc * 16 < tw) {
+      const int j = cc >> 2, sh = (cc & 3) * 16;
+      const u64* B0 = &s.bits[ly * T::WPR];
+      const u64* B1 = &s.bits[(ly - 1) * T::WPR];
+      u64 m0 = B0[j], m1 = B1[j];
+      u64 m0p = j ? B0[j - 1] : 0ull, m1p = j ? B1[j - 1] : 0ull;
+      u64 m0n = j + 1 < T::WPR ? B0[j + 1] : 0ull, m1n = j + 1 < T::WPR ? B1[j + 1] : 0ull;
+      PairMasks pm = pair_masks(m0, m1, m0p, m1p, m0n, m1n, valid_mask(j, tw), j > 0);
+      pts = ((pm.vert >> sh) & 0xFFFFull) | (((pm.da >> sh) & 0xFFFFull) << 16) |
+            (((pm.db >> sh) & 0xFFFFull) << 32);
+      xb = j * 64 + sh;
+    }
+    for (;;) {
+      // wave prefix of the points still to do
+      const int cnt = popc64(pts);
+      int inc = cnt;
+      for (int dl = 1; dl < 64; dl <<= 1) {
+        int t = __shfl_up(inc, dl, 64);
+        if (lane >= dl) inc += t;
+      }
+      const int total = __shfl(inc, 63, 64);
+      if (total == 0) break;
+      const int n = total < scap ? total : scap;
+      int take = n - (inc - cnt);
+      take = take < 0 ? 0 : (take > cnt ? cnt : take);
+      for (int q = inc - cnt; take > 0; take--, q++) {
+        const int kk = __builtin_ctzll(pts);
+        pts &= pts - 1;
+        stage[q] = (u32)(xb + (kk & 15)) | ((u32)ly << 10) | ((u32)(kk >> 4) << 16);
+      }
+      wave_sync();
+      for (int i = lane; i < n; i += 64) {
+        const u32 e = stage[i];
+        const int x = (int)(e & 1023u), row = (int)((e >> 10) & 63u), kind = (int)(e >> 16);
+        const int xu = x + (kind == 1) - (kind == 2);
+        lunion(s.par, (u32)(row * T::TW + run_start(s, row, x)), (u32)((row - 1) * T::TW + run_start(s, row - 1, xu)));
+      }
+      wave_sync();  // the list is rewritten next round
     }
   }
   __syncthreads();
@@ -761,7 +798,7 @@ __device__ void export_tile(TileSmem<T>& s, Acc* bacc, const ImgDesc& d, const T
     return;
   }
 
-  tile_unite<T>(s, tw, th);
+  tile_unite<T>(s, reinterpret_cast<u32*>(bacc), (int)(sizeof(Acc) * T::BCAP / 4), tw, th);
 
   // 6. root ordinal of every run start (border roots first, then interior
   // roots) into par and into the tile state for K6; border node records;

@@ -45,6 +45,9 @@ void emu_wave_exchange(unsigned long long v, unsigned long long* all64);
 #define blockDim (emu_block_dim())
 #define gridDim (emu_grid_dim())
 
+// fibers of a wave meet at wave operations; a fence has no host meaning
+#define __builtin_amdgcn_fence(...) ((void)0)
+
 inline void __syncthreads() { emu_block_barrier(); }
 int emu_block_vote_and(int pred);
 inline int __syncthreads_and(int pred) { return emu_block_vote_and(pred); }
