@@ -41,7 +41,7 @@ EXPORTS = (
     "ccl_variant_info", "ccl_workspace_bytes_v", "ccl_label_v", "ccl_batch_sizes", "ccl_batch_prepare",
     "ccl_label_batch", "ccl_strerror", "ccl_tile_shape",
 )
-TRACE_EVENTS = 11
+TRACE_EVENTS = 12
 
 _lib = None
 

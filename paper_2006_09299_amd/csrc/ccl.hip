@@ -82,7 +82,7 @@ ccl::ImgDesc to_desc(const uint8_t* img, int32_t w, int32_t h, int64_t pitch, co
 }
 
 struct Totals {
-  int64_t tiles = 0, nodes = 0, cells = 0, blocks = 0, items = 0;
+  int64_t tiles = 0, nodes = 0, cells = 0, blocks = 0, items = 0, supers = 0;
   bool too_big() const { return nodes >= INT32_MAX || tiles >= INT32_MAX || blocks >= INT32_MAX; }
 };
 
@@ -93,7 +93,7 @@ int place_batch(const ccl_image_t* imgs, int32_t n, ccl::ImgDesc* ds, Totals& t)
     const ccl_image_t& im = imgs[i];
     if (!image_args_ok(im.img, im.w, im.h, im.pitch, &im.out)) return CCL_EINVAL;
     ccl::ImgDesc d = to_desc(im.img, im.w, im.h, im.pitch, &im.out);
-    ccl::place_image<typename Vt::T>(d, t.tiles, t.nodes, t.cells, t.blocks, t.items);
+    ccl::place_image<typename Vt::T>(d, t.tiles, t.nodes, t.cells, t.blocks, t.items, t.supers);
     if (ds) ds[i] = d;
   }
   return t.too_big() ? CCL_ETOOBIG : CCL_OK;
@@ -107,7 +107,7 @@ int label_one(const uint8_t* img, int32_t w, int32_t h, int64_t pitch, const ccl
     using T = typename Vt::T;
     ccl::ImgDesc d = to_desc(img, w, h, pitch, out);
     Totals t;
-    ccl::place_image<T>(d, t.tiles, t.nodes, t.cells, t.blocks, t.items);
+    ccl::place_image<T>(d, t.tiles, t.nodes, t.cells, t.blocks, t.items, t.supers);
     if (t.too_big()) return CCL_ETOOBIG;
     ccl::Layout L = ccl::make_layout<T>(t.tiles, t.nodes, t.cells, t.blocks);
     if (ws_bytes < L.bytes) return CCL_ENOSPC;
@@ -115,7 +115,7 @@ int label_one(const uint8_t* img, int32_t w, int32_t h, int64_t pitch, const ccl
     HipLauncher hl{static_cast<hipStream_t>(stream)};
     hl.events = events;
     ccl::OneImage src{d};
-    ccl::enqueue<T, Vt::hash>(hl, src, wk, t.tiles, t.items, t.blocks, 1);
+    ccl::enqueue<T, Vt::hash>(hl, src, wk, t.tiles, t.items, t.blocks, 1, t.supers);
     hl.finish();
     return hl.err == hipSuccess ? CCL_OK : CCL_EHIP;
   });
@@ -147,7 +147,7 @@ size_t ccl_workspace_bytes_v(int32_t w, int32_t h, int32_t variant) {
     d.w = w;
     d.h = h;
     Totals t;
-    ccl::place_image<T>(d, t.tiles, t.nodes, t.cells, t.blocks, t.items);
+    ccl::place_image<T>(d, t.tiles, t.nodes, t.cells, t.blocks, t.items, t.supers);
     bytes = ccl::make_layout<T>(t.tiles, t.nodes, t.cells, t.blocks).bytes;
     return CCL_OK;
   });
@@ -176,7 +176,7 @@ int ccl_label_traced(const uint8_t* img, int32_t w, int32_t h, int64_t pitch, co
 
 const char* ccl_kernel_name(int k) {
   static const char* names[CCL_TRACE_EVENTS - 1] = {
-      "k_tile_export", "k_border_merge", "k_reduce_roots", "k_leaders",
+      "k_tile_export", "k_seam_local", "k_border_merge", "k_reduce_roots", "k_leaders",
       "k_scan_reduce", "k_scan_blocks", "k_scan_apply", "k_emit_border", "k_node_canon", "k_tile_emit"};
   return k >= 0 && k < CCL_TRACE_EVENTS - 1 ? names[k] : nullptr;
 }
@@ -216,7 +216,7 @@ int ccl_label_batch(const ccl_image_t* imgs, int32_t n, int32_t variant, const v
     ccl::Work wk = ccl::make_work(L, ws);
     HipLauncher hl{static_cast<hipStream_t>(stream)};
     ccl::ManyImages src{static_cast<const ccl::ImgDesc*>(dev_desc), n};
-    ccl::enqueue<T, Vt::hash>(hl, src, wk, t.tiles, t.items, t.blocks, n);
+    ccl::enqueue<T, Vt::hash>(hl, src, wk, t.tiles, t.items, t.blocks, n, t.supers);
     return hl.err == hipSuccess ? CCL_OK : CCL_EHIP;
   });
 }

@@ -89,6 +89,7 @@ struct ImgDesc {
   int64_t blk0;      // first scan block
   int64_t it0;       // first border-merge work item
   int64_t nit;       // border-merge work items
+  int64_t s0;        // first super-tile (SUP x SUP tiles) of this image
 };
 
 enum { DF_VEC_IN = 1, DF_VEC_LAB = 2 };
@@ -120,6 +121,7 @@ struct Work {
 };
 
 constexpr u32 HI = 0x80000000u;
+constexpr int SUP = 4;                  // tiles per side of a super-tile (seams merged in LDS)
 constexpr int SCAN_T = 256;             // threads of the scan kernels
 constexpr int SCAN_B = SCAN_T * 4;      // entries per scan block
 
@@ -703,6 +705,7 @@ struct OneImage {
   __device__ const ImgDesc& by_item(int64_t) const { return d; }
   __device__ const ImgDesc& by_block(int64_t) const { return d; }
   __device__ const ImgDesc& by_index(int64_t) const { return d; }
+  __device__ const ImgDesc& by_super(int64_t) const { return d; }
   __device__ int64_t count() const { return 1; }
 };
 
@@ -724,6 +727,7 @@ struct ManyImages {
   __device__ const ImgDesc& by_item(int64_t i) const { return search(i, [](const ImgDesc& d) { return d.it0; }); }
   __device__ const ImgDesc& by_block(int64_t b) const { return search(b, [](const ImgDesc& d) { return d.blk0; }); }
   __device__ const ImgDesc& by_index(int64_t i) const { return ds[i]; }
+  __device__ const ImgDesc& by_super(int64_t v) const { return search(v, [](const ImgDesc& d) { return d.s0; }); }
   __device__ int64_t count() const { return n; }
 };
 
@@ -956,6 +960,109 @@ __host__ __device__ inline int64_t merge_items(int w, int h, int ntx, int nty) {
   return (int64_t)(nty - 1) * nwr + (int64_t)(ntx - 1) * h + 2 * nwr + 2 * (int64_t)h;
 }
 
+// ---------------------------------------------------------------------------
+// K2a: seams inside a super-tile (SUP x SUP tiles) merged in LDS.  The border
+// nodes of the super-tile's tiles get local indices (tile k = row * SUP +
+// column inside the super-tile, times BCAP, plus the slot), which are in the
+// same order as their global ids, so union by minimum agrees with the global
+// union-find.  Every union point of a seam between two tiles of the
+// super-tile whose two pixels lie in it is done here; k_border_merge does the
+// rest (seams on super-tile edges, diagonals leaving a super-tile, the
+// exterior).  Afterwards every node points at its local root.
+
+template <class T>
+__device__ inline int lnode_of(const Work& wk, const ImgDesc& d, int tx0, int ty0, int tx, int ty, u16 slot) {
+  (void)wk;
+  (void)d;
+  return ((ty - ty0) * SUP + (tx - tx0)) * T::BCAP + slot;
+}
+
+template <class T, class Src>
+__global__ void __launch_bounds__(256) k_seam_local(Src src, Work wk) {
+  constexpr int NL = SUP * SUP * T::BCAP;
+  static_assert(NL < 65536 && NL % 2 == 0, "local node index fits 16 bits");
+  __shared__ u32 lpw[NL / 2];  // 16-bit entries; 32-bit words for the links
+  u16* lp = reinterpret_cast<u16*>(lpw);
+  const int tid = threadIdx.x;
+  const int64_t gs = blockIdx.x;
+  const ImgDesc& d = src.by_super(gs);
+  const int64_t ls = gs - d.s0;
+  const int nstx = (d.ntx + SUP - 1) / SUP;
+  const int tx0 = (int)(ls % nstx) * SUP, ty0 = (int)(ls / nstx) * SUP;
+  const int ntxs = d.ntx - tx0 < SUP ? d.ntx - tx0 : SUP;
+  const int ntys = d.nty - ty0 < SUP ? d.nty - ty0 : SUP;
+  for (int l = tid; l < NL; l += 256) lp[l] = (u16)l;
+  __syncthreads();
+
+  const int xs0 = tx0 * T::TW;
+  const int xs1 = (tx0 + ntxs) * T::TW < d.w ? (tx0 + ntxs) * T::TW : d.w;  // pixel range [xs0, xs1)
+  // horizontal seams between tile rows ty0 + e - 1 and ty0 + e, 16 pixels per item
+  const int nchk = (xs1 - xs0 + 15) / 16;
+  const int nh = (ntys - 1) * nchk;
+  // vertical seams between tile columns tx0 + e - 1 and tx0 + e, one image row per item
+  const int y0s = ty0 * T::TH;
+  const int rows = (ty0 + ntys) * T::TH < d.h ? (ty0 + ntys) * T::TH - y0s : d.h - y0s;
+  const int nv = (ntxs - 1) * rows;
+  for (int it = tid; it < nh + nv; it += 256) {
+    if (it < nh) {
+      const int e = ty0 + 1 + it / nchk;
+      const int x16 = xs0 + (it % nchk) * 16;
+      const int jw = x16 >> 6, sh = x16 & 63;
+      u64 m0 = seam_bits<T>(wk, d, e, jw, false), m1 = seam_bits<T>(wk, d, e - 1, jw, true);
+      u64 m0p = seam_bits<T>(wk, d, e, jw - 1, false), m1p = seam_bits<T>(wk, d, e - 1, jw - 1, true);
+      u64 m0n = seam_bits<T>(wk, d, e, jw + 1, false), m1n = seam_bits<T>(wk, d, e - 1, jw + 1, true);
+      PairMasks pm = pair_masks(m0, m1, m0p, m1p, m0n, m1n, valid_mask(jw, d.w), jw > 0);
+      u64 pts = ((pm.vert >> sh) & 0xFFFFull) | (((pm.da >> sh) & 0xFFFFull) << 16) |
+                (((pm.db >> sh) & 0xFFFFull) << 32);
+      while (pts) {
+        const int k = __builtin_ctzll(pts);
+        pts &= pts - 1;
+        const int x = x16 + (k & 15);
+        const int xu = x + (k >> 4 == 1) - (k >> 4 == 2);
+        if (xu < xs0 || xu >= xs1) continue;  // leaves the super-tile: k_border_merge
+        const int64_t gl = d.tile0 + (int64_t)e * d.ntx + x / T::TW;
+        const int64_t gu = d.tile0 + (int64_t)(e - 1) * d.ntx + xu / T::TW;
+        const int a = lnode_of<T>(wk, d, tx0, ty0, x / T::TW, e, wk.bidx_top[gl * T::TW + x % T::TW]);
+        const int b = lnode_of<T>(wk, d, tx0, ty0, xu / T::TW, e - 1, wk.bidx_bot[gu * T::TW + xu % T::TW]);
+        lunion(lp, (u32)a, (u32)b);
+      }
+    } else {
+      const int q = it - nh;
+      const int e = tx0 + 1 + q / rows, y = y0s + q % rows;
+      const int ly = y % T::TH, ty = y / T::TH;
+      const int a = col_bit<T>(wk, d, e - 1, y, true), b = col_bit<T>(wk, d, e, y, false);
+      int c = -1, dd = -1;
+      if (ly > 0) {
+        c = col_bit<T>(wk, d, e - 1, y - 1, true);
+        dd = col_bit<T>(wk, d, e, y - 1, false);
+      }
+      const int64_t gL = d.tile0 + (int64_t)ty * d.ntx + (e - 1), gR = d.tile0 + (int64_t)ty * d.ntx + e;
+      auto left = [&](int yy) { return lnode_of<T>(wk, d, tx0, ty0, e - 1, ty, wk.bidx_right[gL * T::TH + yy % T::TH]); };
+      auto right = [&](int yy) { return lnode_of<T>(wk, d, tx0, ty0, e, ty, wk.bidx_left[gR * T::TH + yy % T::TH]); };
+      if (a == b && !(ly > 0 && c == a && dd == b)) lunion(lp, (u32)left(y), (u32)right(y));
+      if (ly > 0) {
+        if (b && c && !a && !dd) lunion(lp, (u32)right(y), (u32)left(y - 1));
+        if (a && dd && !b && !c) lunion(lp, (u32)left(y), (u32)right(y - 1));
+      }
+    }
+  }
+  __syncthreads();
+
+  // every node of the super-tile points at its local root
+  for (int l = tid; l < NL; l += 256) {
+    const int k = l / T::BCAP, slot = l % T::BCAP;
+    const int tx = tx0 + k % SUP, ty = ty0 + k / SUP;
+    if (tx - tx0 >= ntxs || ty - ty0 >= ntys) continue;
+    const int64_t lt = (int64_t)ty * d.ntx + tx;
+    if (slot >= wk.nbt[d.tile0 + lt]) continue;
+    const u32 r = lroot(lp, (u32)l);
+    if (r == (u32)l) continue;
+    const int kr = (int)r / T::BCAP, sr = (int)r % T::BCAP;
+    const int64_t ltr = (int64_t)(ty0 + kr / SUP) * d.ntx + tx0 + kr % SUP;
+    wk.gpar[tile_node_base<T>(d, lt) + slot] = (int32_t)(tile_node_base<T>(d, ltr) + sr);
+  }
+}
+
 template <class T, class Src>
 __global__ void __launch_bounds__(256) k_border_merge(Src src, Work wk, int64_t total) {
   const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -968,12 +1075,22 @@ __global__ void __launch_bounds__(256) k_border_merge(Src src, Work wk, int64_t 
   const int64_t nV = (int64_t)(d.ntx - 1) * d.h;
   if (i < nH) {  // horizontal seam: bottom row of tile row e-1 above top row of tile row e
     int e = (int)(i / nwr) + 1, jw = (int)(i % nwr);
+    // seams inside a super-tile were merged by k_seam_local, except for the
+    // diagonals that leave the super-tile at its left / right edge
+    constexpr int SW = SUP * T::WPR;  // words per super-tile column
+    const bool inner = e % SUP != 0;
+    if (inner && jw % SW != 0 && jw % SW != SW - 1) return;
     u64 m0 = seam_bits<T>(wk, d, e, jw, false), m1 = seam_bits<T>(wk, d, e - 1, jw, true);
     u64 m0p = seam_bits<T>(wk, d, e, jw - 1, false), m1p = seam_bits<T>(wk, d, e - 1, jw - 1, true);
     u64 m0n = seam_bits<T>(wk, d, e, jw + 1, false), m1n = seam_bits<T>(wk, d, e - 1, jw + 1, true);
     PairMasks pm = pair_masks(m0, m1, m0p, m1p, m0n, m1n, valid_mask(jw, d.w), jw > 0);
     int xb = jw * 64;
     u64 m = pm.vert;
+    if (inner) {  // only the diagonals that cross a super-tile column edge
+      m = 0;
+      pm.da &= (jw % SW == SW - 1) ? (1ull << 63) : 0ull;
+      pm.db &= (jw % SW == 0) ? 1ull : 0ull;
+    }
     while (m) {
       int x = xb + __builtin_ctzll(m);
       m &= m - 1;
@@ -996,6 +1113,7 @@ __global__ void __launch_bounds__(256) k_border_merge(Src src, Work wk, int64_t 
   i -= nH;
   if (i < nV) {  // vertical seam between tile columns e-1 and e, image row y
     int e = (int)(i / d.h) + 1, y = (int)(i % d.h);
+    if (e % SUP != 0) return;  // inside a super-tile: merged by k_seam_local
     int ly = y % T::TH;
     int a = col_bit<T>(wk, d, e - 1, y, true), b = col_bit<T>(wk, d, e, y, false);
     int c = -1, dd = -1;
@@ -1797,7 +1915,7 @@ inline Work make_work(const Layout& L, void* ws) {
 // per-image geometry; fills the derived fields of d given running offsets
 template <class T>
 inline void place_image(ImgDesc& d, int64_t& tiles, int64_t& nodes, int64_t& cells, int64_t& blocks,
-                        int64_t& items) {
+                        int64_t& items, int64_t& supers) {
   d.ntx = (d.w + T::TW - 1) / T::TW;
   d.nty = (d.h + T::TH - 1) / T::TH;
   int64_t nt = (int64_t)d.ntx * d.nty;
@@ -1809,6 +1927,8 @@ inline void place_image(ImgDesc& d, int64_t& tiles, int64_t& nodes, int64_t& cel
   d.blk0 = blocks;
   d.it0 = items;
   d.nit = merge_items<T>(d.w, d.h, d.ntx, d.nty);
+  d.s0 = supers;
+  supers += (int64_t)((d.ntx + SUP - 1) / SUP) * ((d.nty + SUP - 1) / SUP);
   tiles += nt;
   nodes += 1 + nt * T::BCAP;
   cells += nc;
@@ -1822,8 +1942,9 @@ inline void place_image(ImgDesc& d, int64_t& tiles, int64_t& nodes, int64_t& cel
 // global atomics per node.
 template <class T, bool HASH, class Src, class Launcher>
 inline void enqueue(Launcher& L, const Src& src, const Work& wk, int64_t tiles, int64_t items, int64_t blocks,
-                    int64_t nimages) {
+                    int64_t nimages, int64_t supers) {
   L.launch(k_tile_export<T, Src>, tiles, T::NT, src, wk);
+  L.launch(k_seam_local<T, Src>, supers, 256, src, wk);
   if (items > 0) L.launch(k_border_merge<T, Src>, (items + 255) / 256, 256, src, wk, items);
   if (HASH) L.launch(k_reduce_roots<T, Src>, (tiles + RH_TILES - 1) / RH_TILES, RH_T, src, wk, tiles);
   else L.launch(k_reduce_direct<T, Src>, tiles, 64, src, wk);

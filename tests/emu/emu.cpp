@@ -247,19 +247,19 @@ void run_images(std::vector<Image>& ims, bool batch) {
   };
   EmuLauncher L;
   auto run = [&](std::vector<ccl::ImgDesc>& ds) {
-    int64_t tiles = 0, nodes = 0, cells = 0, blocks = 0, items = 0;
-    for (auto& d : ds) ccl::place_image<T>(d, tiles, nodes, cells, blocks, items);
+    int64_t tiles = 0, nodes = 0, cells = 0, blocks = 0, items = 0, supers = 0;
+    for (auto& d : ds) ccl::place_image<T>(d, tiles, nodes, cells, blocks, items, supers);
     ccl::Layout lay = ccl::make_layout<T>(tiles, nodes, cells, blocks);
     std::vector<unsigned char> ws(lay.bytes);
     memset(ws.data(), 0xA5, ws.size());  // garbage: the path must not rely on zeroed scratch
     ccl::Work wk = ccl::make_work(lay, ws.data());
     if (ds.size() == 1 && !batch) {
       ccl::OneImage src{ds[0]};
-      ccl::enqueue<T, true>(L, src, wk, tiles, items, blocks, 1);
+      ccl::enqueue<T, true>(L, src, wk, tiles, items, blocks, 1, supers);
     } else {
       ccl::ManyImages src{ds.data(), (int32_t)ds.size()};
-      if (tiles % 2) ccl::enqueue<T, false>(L, src, wk, tiles, items, blocks, (int64_t)ds.size());
-      else ccl::enqueue<T, true>(L, src, wk, tiles, items, blocks, (int64_t)ds.size());
+      if (tiles % 2) ccl::enqueue<T, false>(L, src, wk, tiles, items, blocks, (int64_t)ds.size(), supers);
+      else ccl::enqueue<T, true>(L, src, wk, tiles, items, blocks, (int64_t)ds.size(), supers);
     }
   };
   if (batch) {
