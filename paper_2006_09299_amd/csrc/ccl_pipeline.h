@@ -507,6 +507,17 @@ __device__ void tile_unite(TileSmem<T>& s, u32* stage_all, int stage_words, int 
             (((pm.db >> sh) & 0xFFFFull) << 32);
       xb = j * 64 + sh;
     }
+    if (!__ballot(popc64(pts) > 2)) {
+      // few points per lane in this wave: each lane does its own
+      while (pts) {
+        const int kk = __builtin_ctzll(pts);
+        pts &= pts - 1;
+        const int x = xb + (kk & 15);
+        const int xu = x + (kk >> 4 == 1) - (kk >> 4 == 2);
+        lunion(s.par, (u32)(ly * T::TW + run_start(s, ly, x)), (u32)((ly - 1) * T::TW + run_start(s, ly - 1, xu)));
+      }
+      continue;
+    }
     for (;;) {
       // wave prefix of the points still to do
       const int cnt = popc64(pts);
@@ -1509,9 +1520,13 @@ struct EmitSmem {
 // canonical id of root ordinal o
 template <class T>
 __device__ inline int32_t canon_of(const EmitSmem<T>& s, int o) {
-  if (o < s.nb) return s.bcanon[o];
-  const u32 v = s.rt.o.icanon[o - s.nb];
-  return s.rowbase[v >> 8] + (int32_t)(v & 0xFFu);
+  // both tables are read (no divergent branch), the right one selected
+  const int nb = s.nb;
+  const bool border = o < nb;
+  const int32_t cb = s.bcanon[border ? o : 0];
+  const u32 v = s.rt.o.icanon[border ? 0 : o - nb];
+  const int32_t ci = s.rowbase[v >> 8] + (int32_t)(v & 0xFFu);
+  return border ? cb : ci;
 }
 
 template <class T>
@@ -1775,13 +1790,15 @@ __global__ void __launch_bounds__(256) k_tile_emit(Src src, Work wk) {
 #pragma unroll
     for (int k = 0; k < RPT; k++) {
       const int r = tid + k * T::NT;
-      rc[k] = r < nruns ? canon_of(s, s.rt.o.ordr[r]) : 0;
+      if (r >= nruns) break;
+      rc[k] = canon_of(s, s.rt.o.ordr[r]);
     }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < RPT; k++) {
       const int r = tid + k * T::NT;
-      if (r < nruns) s.rt.rcan[r] = rc[k];
+      if (r >= nruns) break;
+      s.rt.rcan[r] = rc[k];
     }
     if (tid < th) s.lcanon[tid] = lcv;
     __syncthreads();
