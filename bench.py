@@ -256,6 +256,7 @@ def run_batch(n_images: int, steps: int, warmup: int):
     loop_ms = a.elapsed_time(b) / steps
     out = {"images": n_images, "Gpixel": round(px / 1e9, 4), "variant": variant,
            "tile": list(ccl.variant_info(variant)[:2]), "hash_reduce": ccl.variant_info(variant)[2],
+           "threads": ccl.variant_info(variant)[3],
            "graph_ms_per_batch": round(batch_ms, 3), "Gpixel_s": round(px / (batch_ms / 1e3) / 1e9, 2),
            "batch_latency_ms_p50": round(lat_ms[len(lat_ms) // 2], 3), "batch_latency_ms_max": round(lat_ms[-1], 3),
            "per_image_loop_ms": round(loop_ms, 3),

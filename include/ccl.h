@@ -110,9 +110,10 @@ const char *ccl_kernel_name(int k);
 /* [host] Number of compiled variants. */
 int32_t ccl_num_variants(void);
 
-/* [host] Tile rows, tile columns and reduction (1 = LDS hash, 0 = direct
- * atomics) of `variant`; CCL_EINVAL for an unknown index. */
-int ccl_variant_info(int32_t variant, int32_t *tile_h, int32_t *tile_w, int32_t *hash_reduce);
+/* [host] Tile rows, tile columns, reduction (1 = LDS hash, 0 = direct
+ * atomics) and threads per tile workgroup of `variant` (any output pointer
+ * may be NULL); CCL_EINVAL for an unknown index. */
+int ccl_variant_info(int32_t variant, int32_t *tile_h, int32_t *tile_w, int32_t *hash_reduce, int32_t *threads);
 
 /* [host] Workspace bytes of `variant` for a w x h image (pure; 0 on bad input). */
 size_t ccl_workspace_bytes_v(int32_t w, int32_t h, int32_t variant);

@@ -15,24 +15,26 @@ namespace {
 
 static_assert(sizeof(ccl::Feature) == sizeof(ccl_feature_t), "feature record layout");
 
-template <int TH, int TW, bool HASH>
+template <int TH, int TW, bool HASH, int NT = 256>
 struct V {
-  using T = ccl::Tile<TH, TW>;
+  using T = ccl::Tile<TH, TW, NT>;
   static constexpr bool hash = HASH;
 };
 
-// variant index -> (tile rows, tile columns, reduction)
-constexpr int NVARIANTS = 6;
+// variant index -> (tile rows, tile columns, reduction, workgroup size)
+constexpr int NVARIANTS = 8;
 
 template <class F>
 int with_variant(int v, F&& f) {
   switch (v) {
-    case 0: return f(V<32, 128, true>{});
+    case 0: return f(V<64, 128, true, 512>{});
     case 1: return f(V<32, 128, false>{});
     case 2: return f(V<16, 128, true>{});
-    case 3: return f(V<32, 256, true>{});
+    case 3: return f(V<32, 256, true, 512>{});
     case 4: return f(V<64, 128, true>{});
-    case 5: return f(V<16, 256, true>{});
+    case 5: return f(V<32, 128, true>{});
+    case 6: return f(V<16, 256, true>{});
+    case 7: return f(V<32, 256, true>{});
     default: return CCL_EINVAL;
   }
 }
@@ -127,12 +129,13 @@ extern "C" {
 
 int32_t ccl_num_variants(void) { return NVARIANTS; }
 
-int ccl_variant_info(int32_t variant, int32_t* tile_h, int32_t* tile_w, int32_t* hash_reduce) {
+int ccl_variant_info(int32_t variant, int32_t* tile_h, int32_t* tile_w, int32_t* hash_reduce, int32_t* threads) {
   return with_variant(variant, [&](auto vt) -> int {
     using Vt = decltype(vt);
     if (tile_h) *tile_h = Vt::T::TH;
     if (tile_w) *tile_w = Vt::T::TW;
     if (hash_reduce) *hash_reduce = Vt::hash ? 1 : 0;
+    if (threads) *threads = Vt::T::NT;
     return CCL_OK;
   });
 }
@@ -233,6 +236,6 @@ const char* ccl_strerror(int code) {
   }
 }
 
-void ccl_tile_shape(int32_t* tile_h, int32_t* tile_w) { ccl_variant_info(0, tile_h, tile_w, nullptr); }
+void ccl_tile_shape(int32_t* tile_h, int32_t* tile_w) { ccl_variant_info(0, tile_h, tile_w, nullptr, nullptr); }
 
 }  // extern "C"

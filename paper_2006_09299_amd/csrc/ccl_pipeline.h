@@ -125,7 +125,7 @@ constexpr int SUP = 4;                  // tiles per side of a super-tile (seams
 constexpr int SCAN_T = 256;             // threads of the scan kernels
 constexpr int SCAN_B = SCAN_T * 4;      // entries per scan block
 
-template <int TH_, int TW_>
+template <int TH_, int TW_, int NT_ = 256>
 struct Tile {
   static constexpr int TH = TH_;
   static constexpr int TW = TW_;
@@ -135,7 +135,7 @@ struct Tile {
   static constexpr int CPR = TW / 16;      // 16-pixel chunks per row
   static constexpr int NCH = TH * CPR;     // chunks per tile
   static constexpr int BCAP = 2 * (TH + TW);  // >= border pixels >= border nodes
-  static constexpr int NT = 256;           // threads per tile workgroup
+  static constexpr int NT = NT_;           // threads per tile workgroup
   static constexpr int CAPI = 256;         // interior accumulators per pass
   static_assert(TW % 64 == 0 && TW <= 256, "tile width (a row rank fits 8 bits)");
   static_assert(TH >= 1 && TH <= 64, "tile height");
@@ -921,7 +921,7 @@ __device__ void export_tile(TileSmem<T>& s, Acc* bacc, const ImgDesc& d, const T
 }
 
 template <class T, class Src>
-__global__ void __launch_bounds__(256) k_tile_export(Src src, Work wk) {
+__global__ void __launch_bounds__(T::NT) k_tile_export(Src src, Work wk) {
   __shared__ TileSmem<T> s;
   __shared__ Acc bacc[T::BCAP];
   const int64_t gt = blockIdx.x;
@@ -1556,7 +1556,7 @@ __device__ inline void for_runs(const EmitSmem<T>& s, int ly, int cc, int tw, Fn
 }
 
 template <class T, class Src>
-__global__ void __launch_bounds__(256) k_tile_emit(Src src, Work wk) {
+__global__ void __launch_bounds__(T::NT) k_tile_emit(Src src, Work wk) {
   __shared__ EmitSmem<T> s;
   __shared__ Acc iacc[T::CAPI];
   const int64_t gt = blockIdx.x;

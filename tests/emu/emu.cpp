@@ -309,6 +309,7 @@ int main(int argc, char** argv) {
     case 3: run_images<ccl::Tile<5, 192>>(ims, batch); break;
     case 4: run_images<ccl::Tile<64, 64>>(ims, batch); break;
     case 5: run_images<ccl::Tile<1, 64>>(ims, batch); break;
+    case 6: run_images<ccl::Tile<16, 128, 512>>(ims, batch); break;
     default: fprintf(stderr, "bad tile config\n"); return 2;
   }
   FILE* fo = fopen(argv[4], "wb");

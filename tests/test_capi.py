@@ -88,9 +88,9 @@ def test_variants_are_described():
     assert n >= 2
     seen = set()
     for v in range(n):
-        th, tw, hs = _capi.variant_info(v)
-        assert th >= 1 and tw % 64 == 0
-        seen.add((th, tw, hs))
+        th, tw, hs, nt = _capi.variant_info(v)
+        assert th >= 1 and tw % 64 == 0 and nt % 64 == 0
+        seen.add((th, tw, hs, nt))
         assert _capi.workspace_bytes(1000, 700, v) > 0
     assert len(seen) == n
     assert _capi.variant_info(0)[:2] == _capi.tile_shape()

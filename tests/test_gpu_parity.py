@@ -1,8 +1,8 @@
 """GPU parity: libccl.so on the MI355X against the CPU oracle, element by element.
 
 Integer outputs, so the bar is bit-exact: labels, features, parent, colour,
-number of labels and Euler number.  Sizes span many 32 x 128 tiles with
-ragged tails; full-size workloads (8192^2 sweep, 16384^2 structured) are
+number of labels and Euler number.  Sizes span many tiles (and 4 x 4-tile
+super-tiles) with ragged tails; full-size workloads (8192^2 sweep, 16384^2 structured) are
 compared in full where the oracle finishes in seconds and checked by
 size-independent properties everywhere."""
 import sys
@@ -105,7 +105,8 @@ def test_random_shapes_span_tiles_and_tails():
 
 
 @pytest.mark.parametrize("h,w", [(1, 1), (1, 2), (2, 1), (1, 1000), (1000, 1), (31, 127), (32, 128), (33, 129),
-                                 (64, 256), (65, 257), (97, 383), (3, 130)])
+                                 (63, 127), (64, 128), (64, 256), (65, 257), (97, 383), (3, 130), (255, 511),
+                                 (256, 512), (257, 513)])
 def test_edge_shapes(h, w):
     for p in (0.0, 0.3, 0.6, 1.0):
         img = synth.bernoulli_blocks(h, w, p, 1, h * 7919 + w)
