@@ -138,7 +138,8 @@ struct Tile {
   static constexpr int NT = NT_;           // threads per tile workgroup
   static constexpr int CAPI = 256;         // interior accumulators per pass
   static_assert(TW % 64 == 0 && TW <= 256, "tile width (a row rank fits 8 bits)");
-  static_assert(TH >= 1 && TH <= 64, "tile height");
+  static_assert(TH >= 1 && TH <= 64, "tile height (a column of the tile fits one wave)");
+  static_assert(NT >= 128 && NT % 64 == 0, "at least two waves per tile");
   static_assert(N < 65536, "positions must fit 16 bits");
   static_assert((long long)N * (TW - 1) < (1ll << 24), "packed Sx field");
   static_assert((long long)N * (TH - 1) < (1ll << 24), "packed Sy field");
@@ -907,16 +908,17 @@ __device__ void export_tile(TileSmem<T>& s, Acc* bacc, const ImgDesc& d, const T
       (right ? wk.bidx_right : wk.bidx_left)[gt * T::TH + ly] = v;
     }
   }
-  for (int t = tid; t < 2 * T::WPR + 2; t += T::NT) {
+  for (int t = tid; t < 2 * T::WPR; t += T::NT) {
     if (t < T::WPR) wk.bits_top[gt * T::WPR + t] = s.bits[t];
-    else if (t < 2 * T::WPR) wk.bits_bot[gt * T::WPR + (t - T::WPR)] = s.bits[(th - 1) * T::WPR + (t - T::WPR)];
-    else {
-      int right = t - 2 * T::WPR;
-      u64 col = 0;
-      int x = right ? tw - 1 : 0;
-      for (int ly = 0; ly < th; ly++) col |= ((s.bits[ly * T::WPR + (x >> 6)] >> (x & 63)) & 1ull) << ly;
-      wk.bits_lr[gt * 2 + right] = col;
-    }
+    else wk.bits_bot[gt * T::WPR + (t - T::WPR)] = s.bits[(th - 1) * T::WPR + (t - T::WPR)];
+  }
+  // left / right column bits (bit = row): one lane per row of waves 0 / 1
+  if (tid < 128) {
+    const int right = tid >> 6, ly = tid & 63;
+    const int x = right ? tw - 1 : 0;
+    const bool fg = ly < th && ((s.bits[ly * T::WPR + (x >> 6)] >> (x & 63)) & 1ull);
+    const u64 col = __ballot(fg);
+    if (ly == 0) wk.bits_lr[gt * 2 + right] = col;
   }
 }
 
