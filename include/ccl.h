@@ -101,11 +101,12 @@ int ccl_label_traced(const uint8_t *img, int32_t w, int32_t h, int64_t pitch, co
 /* [host] Name of kernel k (0..CCL_TRACE_EVENTS-2) in launch order, or NULL. */
 const char *ccl_kernel_name(int k);
 
-/* Variants: the path compiled for several tile shapes and for two ways of
- * summing the partial features of components that cross tiles (an LDS hash
- * table per group of tiles, or direct global atomics).  All variants give
- * identical results; they differ in speed per workload.  Variant 0 is the
- * default of ccl_label. */
+/* Variants: the path compiled for several tile shapes, workgroup sizes and
+ * two ways of summing the partial features of components that cross tiles
+ * (an LDS hash table per group of tiles, or direct global atomics).  All
+ * variants give identical results; they differ in speed per workload.
+ * Variant 0 (64 x 128 tiles, 512 threads, LDS hash) is the default of
+ * ccl_label. */
 
 /* [host] Number of compiled variants. */
 int32_t ccl_num_variants(void);
