@@ -969,8 +969,12 @@ __device__ inline int col_bit(const Work& wk, const ImgDesc& d, int tcol, int y,
 
 template <class T>
 __host__ __device__ inline int64_t merge_items(int w, int h, int ntx, int nty) {
-  int64_t nwr = (w + 63) / 64;
-  return (int64_t)(nty - 1) * nwr + (int64_t)(ntx - 1) * h + 2 * nwr + 2 * (int64_t)h;
+  // horizontal seams on super-tile row edges (every word), horizontal seams
+  // inside super-tiles (the two edge words of each super-tile column),
+  // vertical seams on super-tile column edges (every row), exterior
+  const int64_t nwr = (w + 63) / 64, nstx = (ntx + SUP - 1) / SUP;
+  const int64_t hb = (nty - 1) / SUP, hi = (nty - 1) - hb, vb = (ntx - 1) / SUP;
+  return hb * nwr + hi * 2 * nstx + vb * h + 2 * nwr + 2 * (int64_t)h;
 }
 
 // ---------------------------------------------------------------------------
@@ -1084,15 +1088,27 @@ __global__ void __launch_bounds__(256) k_border_merge(Src src, Work wk, int64_t 
   int64_t i = gi - d.it0;
   const int nwr = (d.w + 63) >> 6;
   const int ext = (int)d.node0;
-  const int64_t nH = (int64_t)(d.nty - 1) * nwr;
-  const int64_t nV = (int64_t)(d.ntx - 1) * d.h;
+  constexpr int SW = SUP * T::WPR;  // words per super-tile column
+  const int nstx = (d.ntx + SUP - 1) / SUP;
+  const int64_t hb = (d.nty - 1) / SUP, hi = (d.nty - 1) - hb, vb = (d.ntx - 1) / SUP;
+  const int64_t nH = hb * nwr + hi * 2 * nstx;
+  const int64_t nV = vb * d.h;
   if (i < nH) {  // horizontal seam: bottom row of tile row e-1 above top row of tile row e
-    int e = (int)(i / nwr) + 1, jw = (int)(i % nwr);
-    // seams inside a super-tile were merged by k_seam_local, except for the
-    // diagonals that leave the super-tile at its left / right edge
-    constexpr int SW = SUP * T::WPR;  // words per super-tile column
-    const bool inner = e % SUP != 0;
-    if (inner && jw % SW != 0 && jw % SW != SW - 1) return;
+    int e, jw;
+    bool inner;
+    if (i < hb * nwr) {  // on a super-tile row edge: every word
+      e = SUP * (int)(i / nwr + 1);
+      jw = (int)(i % nwr);
+      inner = false;
+    } else {  // inside super-tiles, merged by k_seam_local except for the
+              // diagonals that leave a super-tile column at its edge words
+      const int64_t q = (i - hb * nwr) / (2 * nstx);
+      const int r = (int)((i - hb * nwr) % (2 * nstx));
+      e = (int)(q + 1 + q / (SUP - 1));  // the q-th seam index that is not a multiple of SUP
+      jw = (r >> 1) * SW + ((r & 1) ? SW - 1 : 0);
+      if (jw >= nwr) return;
+      inner = true;
+    }
     u64 m0 = seam_bits<T>(wk, d, e, jw, false), m1 = seam_bits<T>(wk, d, e - 1, jw, true);
     u64 m0p = seam_bits<T>(wk, d, e, jw - 1, false), m1p = seam_bits<T>(wk, d, e - 1, jw - 1, true);
     u64 m0n = seam_bits<T>(wk, d, e, jw + 1, false), m1n = seam_bits<T>(wk, d, e - 1, jw + 1, true);
@@ -1124,9 +1140,8 @@ __global__ void __launch_bounds__(256) k_border_merge(Src src, Work wk, int64_t 
     return;
   }
   i -= nH;
-  if (i < nV) {  // vertical seam between tile columns e-1 and e, image row y
-    int e = (int)(i / d.h) + 1, y = (int)(i % d.h);
-    if (e % SUP != 0) return;  // inside a super-tile: merged by k_seam_local
+  if (i < nV) {  // vertical seam on a super-tile column edge, between tile columns e-1 and e, image row y
+    int e = SUP * (int)(i / d.h + 1), y = (int)(i % d.h);
     int ly = y % T::TH;
     int a = col_bit<T>(wk, d, e - 1, y, true), b = col_bit<T>(wk, d, e, y, false);
     int c = -1, dd = -1;
@@ -1181,7 +1196,10 @@ __global__ void __launch_bounds__(256) k_border_merge(Src src, Work wk, int64_t 
 // per flush.
 
 constexpr int RH_CAP = 512;      // LDS hash slots
-constexpr int RH_TILES = 32;     // tiles per workgroup
+// tiles per workgroup: larger groups send fewer atomics to the roots of
+// components that span many tiles (the exterior above all)
+template <class T>
+constexpr int rh_tiles() { return T::N > 4096 ? 64 : 32; }
 constexpr int RH_T = 256;        // threads
 constexpr int RH_EMPTY = -1;
 
@@ -1203,14 +1221,15 @@ __device__ inline void rootacc_clear(RootAcc& a) {
 
 template <class T, class Src>
 __global__ void __launch_bounds__(RH_T) k_reduce_roots(Src src, Work wk, int64_t tiles) {
-  static_assert(RH_TILES <= 64, "one wave scans the group");
+  constexpr int RHT = rh_tiles<T>();
+  static_assert(RHT <= 64, "one wave scans the group");
   __shared__ RootAcc tab[RH_CAP];
-  __shared__ int pre[RH_TILES + 1];
-  __shared__ int64_t tbase[RH_TILES];
+  __shared__ int pre[RHT + 1];
+  __shared__ int64_t tbase[RHT];
   __shared__ int used;
   const int tid = threadIdx.x;
-  const int64_t t0 = (int64_t)blockIdx.x * RH_TILES;
-  const int ntl = tiles - t0 < RH_TILES ? (int)(tiles - t0) : RH_TILES;
+  const int64_t t0 = (int64_t)blockIdx.x * RHT;
+  const int ntl = tiles - t0 < RHT ? (int)(tiles - t0) : RHT;
   for (int i = tid; i < RH_CAP; i += RH_T) rootacc_clear(tab[i]);
   if (tid < 64) {  // node counts of the group's tiles -> exclusive prefix
     int c = 0;
@@ -1225,18 +1244,18 @@ __global__ void __launch_bounds__(RH_T) k_reduce_roots(Src src, Work wk, int64_t
       int t = __shfl_up(inc, dl, 64);
       if (tid >= dl) inc += t;
     }
-    if (tid < RH_TILES) pre[tid] = inc - c;
-    if (tid == RH_TILES - 1) pre[RH_TILES] = inc;
+    if (tid < RHT) pre[tid] = inc - c;
+    if (tid == RHT - 1) pre[RHT] = inc;
   }
   if (tid == 0) used = 0;
   __syncthreads();
-  const int total = pre[RH_TILES];
+  const int total = pre[RHT];
   // the group's nodes as one list, RH_T at a time
   for (int base = 0; base < total; base += RH_T) {
     const int i = base + tid;
     if (i < total) {
       int k = 0;
-      for (int m = 1; m < RH_TILES; m++) k += pre[m] <= i ? 1 : 0;
+      for (int m = 1; m < RHT; m++) k += pre[m] <= i ? 1 : 0;
       const int node = (int)(tbase[k] + (i - pre[k]));
       const Feature f = wk.gacc[node];
       const int32_t key = wk.gkey[node];
@@ -1965,7 +1984,7 @@ inline void enqueue(Launcher& L, const Src& src, const Work& wk, int64_t tiles, 
   L.launch(k_tile_export<T, Src>, tiles, T::NT, src, wk);
   L.launch(k_seam_local<T, Src>, supers, 256, src, wk);
   if (items > 0) L.launch(k_border_merge<T, Src>, (items + 255) / 256, 256, src, wk, items);
-  if (HASH) L.launch(k_reduce_roots<T, Src>, (tiles + RH_TILES - 1) / RH_TILES, RH_T, src, wk, tiles);
+  if (HASH) L.launch(k_reduce_roots<T, Src>, (tiles + rh_tiles<T>() - 1) / rh_tiles<T>(), RH_T, src, wk, tiles);
   else L.launch(k_reduce_direct<T, Src>, tiles, 64, src, wk);
   L.launch(k_leaders<T, Src>, tiles, 64, src, wk);
   L.launch(k_scan_reduce<Src>, blocks, SCAN_T, src, wk);
