@@ -136,7 +136,7 @@ struct Tile {
   static constexpr int NCH = TH * CPR;     // chunks per tile
   static constexpr int BCAP = 2 * (TH + TW);  // >= border pixels >= border nodes
   static constexpr int NT = NT_;           // threads per tile workgroup
-  static constexpr int CAPI = 256;         // interior accumulators per pass
+  static constexpr int CAPI = N >= 8192 ? 512 : 256;  // interior accumulators per pass
   static_assert(TW % 64 == 0 && TW <= 256, "tile width (a row rank fits 8 bits)");
   static_assert(TH >= 1 && TH <= 64, "tile height (a column of the tile fits one wave)");
   static_assert(NT >= 128 && NT % 64 == 0, "at least two waves per tile");
