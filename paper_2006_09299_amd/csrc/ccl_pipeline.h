@@ -677,9 +677,12 @@ __device__ inline void rowsum_flush(RowSum& r, Acc* acc, int ly) {
   if (r.o < 0) return;
   Acc& a = acc[r.o];
   atomicAdd(&a.s, r.s);
-  atomicMin(&a.xmin, r.xmin);
-  atomicMax(&a.xmax, r.xmax);
-  atomicMax(&a.ymax, (u32)ly);
+  // the extremes only ever move outwards: an atomic is needed only when the
+  // value read does not already include this one (reads of one address by
+  // many lanes are served at once, atomics on it one after another)
+  if (r.xmin < ld_wg(&a.xmin)) atomicMin(&a.xmin, r.xmin);
+  if (r.xmax > ld_wg(&a.xmax)) atomicMax(&a.xmax, r.xmax);
+  if ((u32)ly > ld_wg(&a.ymax)) atomicMax(&a.ymax, (u32)ly);
   r.o = -1;
 }
 __device__ inline void rowsum_add(RowSum& r, Acc* acc, int o, int ly, int s0, int e0) {
