@@ -293,7 +293,6 @@ def run_serve(n_requests: int, rate_hz: float = 2000.0, warmup_s: float = 1.0, p
         while i < len(stream) and stream[i].arrival_s <= now:
             srv.submit(i, host[i % pool_images], arrival=start + stream[i].arrival_s)
             i += 1
-        qmax = max(qmax, len(srv.queue))
         for r in srv.step():
             if r.rid >= warm:
                 lat.append(r.done - r.arrival)
@@ -301,12 +300,16 @@ def run_serve(n_requests: int, rate_hz: float = 2000.0, warmup_s: float = 1.0, p
                 t_first = r.arrival if t_first is None else min(t_first, r.arrival)
                 t_last = r.done if t_last is None else max(t_last, r.done)
             srv.release(r.rid)
+        qmax = max(qmax, srv.queued())
+    st = srv.stats()
+    srv.close()
     lat.sort()
     q = lambda f: round(1e3 * lat[min(len(lat) - 1, int(f * len(lat)))], 3)
     span = t_last - t_first
     return {"requests": len(lat), "rate_hz": rate_hz, "offered_Gpixel_s": round(px_done / (len(lat) / rate_hz) / 1e9, 2),
             "Gpixel_s": round(px_done / span / 1e9, 2), "p50_ms": q(0.50), "p99_ms": q(0.99), "max_ms": round(1e3 * lat[-1], 3),
-            "max_queue": qmax, "rejected": srv.rejected, "streams": len(srv.streams), "max_batch": srv.max_batch}
+            "max_queue": qmax, "rejected": srv.rejected, "streams": srv.streams, "max_batch": srv.max_batch,
+            "micro_batches": st.launches, "relaunched": st.relaunched}
 
 
 def cpu_baseline(work, budget_s: float = 15.0):

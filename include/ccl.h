@@ -142,6 +142,89 @@ int ccl_batch_prepare(const ccl_image_t *imgs, int32_t n, int32_t variant, void 
 int ccl_label_batch(const ccl_image_t *imgs, int32_t n, int32_t variant, const void *dev_desc, void *ws,
                     size_t ws_bytes, void *stream);
 
+/* Serving: continuous batching over ccl_label_batch.  The paper labels one
+ * image at a time; this front end runs the same path for a stream of requests
+ * of any sizes.  Requests are admitted in arrival order as soon as a slot and
+ * device memory for their whole footprint are free; everything admitted at one
+ * poll forms a micro-batch, launched on the next idle one of the server's
+ * streams, so that newly admitted work overlaps earlier micro-batches.
+ *
+ * Memory: `pool` [device, caller-owned, >= 256-byte aligned] is sub-allocated
+ * first-fit by the server for every request's input copy, label image and
+ * tables and for each micro-batch's descriptors, workspace and counts; the
+ * server itself allocates no device memory.  It creates its streams (default
+ * priority) and events and grows pinned host staging for descriptors and
+ * counts (hipHostMalloc).  A server is used by one host thread at a time;
+ * servers are independent of each other.
+ *
+ * Errors: CCL_EINVAL (bad argument, duplicate or unknown tag, request not
+ * done), CCL_ENOSPC (a request's footprint exceeds the whole pool), CCL_EHIP
+ * (the HIP runtime failed; the server then returns CCL_EHIP from every call
+ * but ccl_server_destroy). */
+typedef struct ccl_server ccl_server_t;
+
+typedef struct {
+  int32_t max_slots;   /* requests admitted and not yet released, >= 1 */
+  int32_t streams;     /* micro-batches in flight at once, 1..16 */
+  int32_t max_batch;   /* requests per micro-batch, >= 1 */
+  int32_t variant;     /* path variant, 0..ccl_num_variants()-1 */
+  int32_t cap_divisor; /* first table capacity of a w x h request:
+                          min(w*h+1, max(1024, (w*h+1)/cap_divisor)); >= 1 */
+} ccl_server_config_t;
+
+/* A finished request. */
+typedef struct {
+  int64_t tag;
+  int32_t status;    /* CCL_OK, or CCL_ENOSPC: the tables this image needs do not fit the pool
+                        (n_labels holds the number of labels; no outputs) */
+  int32_t w, h;
+  int32_t launches;  /* 1, or 2 when the first table capacity was too small and the request ran
+                        again with exactly n_labels entries */
+  int64_t n_labels, euler;
+  ccl_outputs_t out; /* device pointers into the pool, valid until ccl_server_release(tag);
+                        out.counts = NULL (the counts are n_labels and euler above) */
+} ccl_done_t;
+
+typedef struct {
+  int64_t queued;     /* submitted, not yet admitted */
+  int64_t live;       /* admitted, not yet released (holding pool memory) */
+  int64_t in_flight;  /* micro-batches running */
+  int64_t ready;      /* finished, not yet returned by ccl_server_poll */
+  int64_t pool_used, pool_bytes;
+  int64_t admitted, completed, launches, relaunched;
+} ccl_server_stats_t;
+
+/* [host] Create a server over `pool`; `cfg` NULL takes max_slots 256, streams
+ * 4, max_batch 64, variant 0, cap_divisor 4. */
+int ccl_server_create(void *pool, size_t pool_bytes, const ccl_server_config_t *cfg, ccl_server_t **srv);
+
+/* [host] Pool bytes a w x h request needs when it runs alone (its blocks, one
+ * descriptor, its workspace and its counts, each rounded to 256 bytes). */
+int ccl_server_footprint(const ccl_server_t *srv, int32_t w, int32_t h, size_t *bytes);
+
+/* [host] Queue a request: `img` [host] h rows of `pitch` bytes; it must stay
+ * valid and unchanged until ccl_server_poll reports `tag` (pinned memory
+ * makes the upload asynchronous).  `tag` is the caller's name for the request
+ * and must not name a request that is still unreleased.  Nothing is enqueued
+ * on the device here. */
+int ccl_server_submit(ccl_server_t *srv, const uint8_t *img, int32_t w, int32_t h, int64_t pitch, int64_t tag);
+
+/* [host] One scheduling step, never blocking: collect finished micro-batches,
+ * admit and launch what fits, then copy up to `max_done` finished requests
+ * into `done` [host] in completion order (*n_done of them). */
+int ccl_server_poll(ccl_server_t *srv, ccl_done_t *done, int32_t max_done, int32_t *n_done);
+
+/* [host] Give a finished request's pool memory back.  The caller's own work
+ * on its outputs must have completed. */
+int ccl_server_release(ccl_server_t *srv, int64_t tag);
+
+/* [host] Counters and occupancy. */
+int ccl_server_stats(const ccl_server_t *srv, ccl_server_stats_t *st);
+
+/* [host] Wait for the micro-batches in flight, then free the server's streams,
+ * events and staging.  The pool stays the caller's. */
+int ccl_server_destroy(ccl_server_t *srv);
+
 /* [host] Static message for a CCL_E* code. */
 const char *ccl_strerror(int code);
 

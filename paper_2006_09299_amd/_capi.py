@@ -36,10 +36,40 @@ class ccl_image_t(ctypes.Structure):
     ]
 
 
+class ccl_server_config_t(ctypes.Structure):
+    _fields_ = [
+        ("max_slots", ctypes.c_int32),
+        ("streams", ctypes.c_int32),
+        ("max_batch", ctypes.c_int32),
+        ("variant", ctypes.c_int32),
+        ("cap_divisor", ctypes.c_int32),
+    ]
+
+
+class ccl_done_t(ctypes.Structure):
+    _fields_ = [
+        ("tag", ctypes.c_int64),
+        ("status", ctypes.c_int32),
+        ("w", ctypes.c_int32),
+        ("h", ctypes.c_int32),
+        ("launches", ctypes.c_int32),
+        ("n_labels", ctypes.c_int64),
+        ("euler", ctypes.c_int64),
+        ("out", ccl_outputs_t),
+    ]
+
+
+class ccl_server_stats_t(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "queued", "live", "in_flight", "ready", "pool_used", "pool_bytes", "admitted", "completed", "launches",
+        "relaunched")]
+
+
 EXPORTS = (
     "ccl_workspace_bytes", "ccl_label", "ccl_label_traced", "ccl_kernel_name", "ccl_num_variants",
     "ccl_variant_info", "ccl_workspace_bytes_v", "ccl_label_v", "ccl_batch_sizes", "ccl_batch_prepare",
-    "ccl_label_batch", "ccl_strerror", "ccl_tile_shape",
+    "ccl_label_batch", "ccl_strerror", "ccl_tile_shape", "ccl_server_create", "ccl_server_footprint",
+    "ccl_server_submit", "ccl_server_poll", "ccl_server_release", "ccl_server_stats", "ccl_server_destroy",
 )
 TRACE_EVENTS = 12
 
@@ -93,6 +123,22 @@ def lib():
                                       ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
         L.ccl_strerror.restype = ctypes.c_char_p
         L.ccl_strerror.argtypes = [ctypes.c_int]
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.ccl_server_create.restype = ctypes.c_int
+        L.ccl_server_create.argtypes = [vp, ctypes.c_size_t, ctypes.POINTER(ccl_server_config_t),
+                                        ctypes.POINTER(ctypes.c_void_p)]
+        L.ccl_server_footprint.restype = ctypes.c_int
+        L.ccl_server_footprint.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_size_t)]
+        L.ccl_server_submit.restype = ctypes.c_int
+        L.ccl_server_submit.argtypes = [vp, vp, i32, i32, i64, i64]
+        L.ccl_server_poll.restype = ctypes.c_int
+        L.ccl_server_poll.argtypes = [vp, ctypes.POINTER(ccl_done_t), i32, ctypes.POINTER(i32)]
+        L.ccl_server_release.restype = ctypes.c_int
+        L.ccl_server_release.argtypes = [vp, i64]
+        L.ccl_server_stats.restype = ctypes.c_int
+        L.ccl_server_stats.argtypes = [vp, ctypes.POINTER(ccl_server_stats_t)]
+        L.ccl_server_destroy.restype = ctypes.c_int
+        L.ccl_server_destroy.argtypes = [vp]
         L.ccl_tile_shape.restype = None
         L.ccl_tile_shape.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
         _lib = L

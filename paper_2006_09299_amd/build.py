@@ -10,6 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libccl.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
+SOURCES = ["ccl.hip", "ccl_server.cpp"]  # kernels + C-ABI; serving front end (host code)
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # keep the compiler from forming packed fp32 instructions
@@ -19,9 +20,9 @@ FLAGS = [
 
 
 def build() -> str:
-    src = os.path.join(CSRC, "ccl.hip")
+    srcs = [os.path.join(CSRC, f) for f in SOURCES]
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, *FLAGS, src, "-o", tmp]
+    cmd = [HIPCC, *FLAGS, *srcs, "-o", tmp]
     p = subprocess.run(cmd, capture_output=True, text=True)
     # the host pass does not know the gfx feature flag; that warning is harmless
     noise = [ln for ln in p.stderr.splitlines() if ln.strip() and "packed-fp32-ops" not in ln]

@@ -14,6 +14,7 @@
 namespace {
 
 static_assert(sizeof(ccl::Feature) == sizeof(ccl_feature_t), "feature record layout");
+static_assert(sizeof(ccl::ImgDesc) <= 256, "the serving footprint counts one 256-byte block per descriptor");
 
 template <int TH, int TW, bool HASH, int NT = 256>
 struct V {
