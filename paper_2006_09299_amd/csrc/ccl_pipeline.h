@@ -94,6 +94,14 @@ struct ImgDesc {
 
 enum { DF_VEC_IN = 1, DF_VEC_LAB = 2 };
 
+// Four labels with one 16-byte store that does not keep the line in the
+// caches: the label image is written once and never read back by the path.
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+__device__ inline void store_labels4(int32_t* dst, int32_t a, int32_t b, int32_t c, int32_t e) {
+  i32x4 v = {a, b, c, e};
+  __builtin_nontemporal_store(v, reinterpret_cast<i32x4*>(dst));
+}
+
 // Workspace views (device memory), shared by all images of a launch.
 struct Work {
   int32_t* gpar;     // [nodes] union-find parent of border nodes
@@ -1634,9 +1642,7 @@ __global__ void __launch_bounds__(T::NT) k_tile_emit(Src src, Work wk) {
         if (ly >= th || x >= tw) continue;
         int32_t* dst = d.labels + (int64_t)(y0 + ly) * d.w + x0 + x;
         if (vec && x + 4 <= tw) {
-          int4 v4;
-          v4.x = canon; v4.y = canon; v4.z = canon; v4.w = canon;
-          *reinterpret_cast<int4*>(dst) = v4;
+          store_labels4(dst, canon, canon, canon, canon);
         } else {
           int n = tw - x < 4 ? tw - x : 4;
           for (int k = 0; k < n; k++) dst[k] = canon;
@@ -1867,9 +1873,7 @@ __global__ void __launch_bounds__(T::NT) k_tile_emit(Src src, Work wk) {
       lab[3] = s.rt.rcan[r3];
       int32_t* dst = d.labels + (int64_t)(y0 + ly) * d.w + x0 + x;
       if (vec && x + 4 <= tw) {
-        int4 v4;
-        v4.x = lab[0]; v4.y = lab[1]; v4.z = lab[2]; v4.w = lab[3];
-        *reinterpret_cast<int4*>(dst) = v4;
+        store_labels4(dst, lab[0], lab[1], lab[2], lab[3]);
       } else {
         int n = tw - x < 4 ? tw - x : 4;
         for (int k = 0; k < n; k++) dst[k] = lab[k];
