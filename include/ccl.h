@@ -89,7 +89,7 @@ int ccl_label(const uint8_t *img, int32_t w, int32_t h, int64_t pitch, const ccl
 
 /* Number of HIP events ccl_label_traced records: one before each of the
  * path's ten kernels, in launch order, and one after the last. */
-#define CCL_TRACE_EVENTS 12
+#define CCL_TRACE_EVENTS 11
 
 /* Same work as ccl_label, with `events` [host array of CCL_TRACE_EVENTS
  * hipEvent_t created by the caller] recorded on `stream` around every kernel,

@@ -71,7 +71,7 @@ EXPORTS = (
     "ccl_label_batch", "ccl_strerror", "ccl_tile_shape", "ccl_server_create", "ccl_server_footprint",
     "ccl_server_submit", "ccl_server_poll", "ccl_server_release", "ccl_server_stats", "ccl_server_destroy",
 )
-TRACE_EVENTS = 12
+TRACE_EVENTS = 11
 
 _lib = None
 

@@ -118,7 +118,7 @@ int label_one(const uint8_t* img, int32_t w, int32_t h, int64_t pitch, const ccl
     HipLauncher hl{static_cast<hipStream_t>(stream)};
     hl.events = events;
     ccl::OneImage src{d};
-    ccl::enqueue<T, Vt::hash>(hl, src, wk, t.tiles, t.items, t.blocks, 1, t.supers);
+    ccl::enqueue<T, Vt::hash>(hl, src, wk, t.tiles, t.items, t.blocks, t.supers);
     hl.finish();
     return hl.err == hipSuccess ? CCL_OK : CCL_EHIP;
   });
@@ -181,7 +181,7 @@ int ccl_label_traced(const uint8_t* img, int32_t w, int32_t h, int64_t pitch, co
 const char* ccl_kernel_name(int k) {
   static const char* names[CCL_TRACE_EVENTS - 1] = {
       "k_tile_export", "k_seam_local", "k_border_merge", "k_reduce_roots", "k_leaders",
-      "k_scan_reduce", "k_scan_blocks", "k_scan_apply", "k_emit_border", "k_node_canon", "k_tile_emit"};
+      "k_scan_reduce", "k_scan_apply", "k_emit_border", "k_node_canon", "k_tile_emit"};
   return k >= 0 && k < CCL_TRACE_EVENTS - 1 ? names[k] : nullptr;
 }
 
@@ -220,7 +220,7 @@ int ccl_label_batch(const ccl_image_t* imgs, int32_t n, int32_t variant, const v
     ccl::Work wk = ccl::make_work(L, ws);
     HipLauncher hl{static_cast<hipStream_t>(stream)};
     ccl::ManyImages src{static_cast<const ccl::ImgDesc*>(dev_desc), n};
-    ccl::enqueue<T, Vt::hash>(hl, src, wk, t.tiles, t.items, t.blocks, n, t.supers);
+    ccl::enqueue<T, Vt::hash>(hl, src, wk, t.tiles, t.items, t.blocks, t.supers);
     return hl.err == hipSuccess ? CCL_OK : CCL_EHIP;
   });
 }

@@ -27,10 +27,15 @@
 //                   leave the tile state (bits, root masks, the root ordinal of
 //                   every run) for k_tile_emit.  A one-colour tile skips the
 //                   union-find: one border node, features in closed form.
-//   k_border_merge: unite border nodes across tile edges (horizontal and
-//                   vertical seams, foreground diagonals across corners) and
-//                   background on the image border with the exterior node;
-//                   lock-free union-find in HBM (link by compare-and-swap).
+//   k_seam_local  : unite the seams inside each SUP x SUP group of tiles
+//                   (super-tile) with a 16-bit union-find in LDS over the
+//                   group's border nodes; every non-root node is pointed at
+//                   its super-tile root.
+//   k_border_merge: unite border nodes across the remaining tile edges
+//                   (seams between super-tiles: horizontal and vertical,
+//                   foreground diagonals across corners) and background on
+//                   the image border with the exterior node; lock-free
+//                   union-find in HBM (link by compare-and-swap).
 //   k_reduce_roots: point every border node at its root; the root takes the
 //                   minimum raster key and the sum of the partial features
 //                   (LDS hash per group of tiles first; k_reduce_direct is the
@@ -39,8 +44,11 @@
 //                   of that pixel among the components starting in the same
 //                   row of the same tile.
 //   k_scan_*      : exclusive scan of component starts over (row, tile column)
-//                   in raster order -> canonical id base of every such cell.
+//                   in raster order -> canonical id base of every such cell
+//                   (block totals; then every block adds the totals of the
+//                   image's earlier blocks and scans its own cells).
 //   k_emit_border : canonical id and features of components crossing tiles.
+//   k_node_canon  : canonical id of every border node.
 //   k_tile_emit   : from the tile state: canonical id of every run, the label
 //                   image, features / colour / parent of every component the
 //                   tile owns and its Euler number contribution.
@@ -1439,22 +1447,6 @@ __global__ void __launch_bounds__(SCAN_T) k_scan_reduce(Src src, Work wk) {
 }
 
 template <class Src>
-__global__ void __launch_bounds__(SCAN_T) k_scan_blocks(Src src, Work wk) {
-  __shared__ u32 tmp[SCAN_T];
-  const ImgDesc& d = src.by_index(blockIdx.x);
-  u32 carry = 0;
-  for (int base = 0; base < d.nblk; base += SCAN_T) {
-    int b = base + threadIdx.x;
-    u32 v = b < d.nblk ? (u32)wk.bsum[d.blk0 + b] : 0u;
-    u32 tot;
-    u32 ex = block_excl_scan(v, tmp, tot);
-    if (b < d.nblk) wk.bsum[d.blk0 + b] = (int32_t)(carry + ex);
-    carry += tot;
-  }
-  if (threadIdx.x == 0 && d.counts) d.counts[0] = 1 + (int64_t)carry;
-}
-
-template <class Src>
 __global__ void __launch_bounds__(SCAN_T) k_scan_apply(Src src, Work wk) {
   __shared__ u32 tmp[SCAN_T];
   const int64_t gb = blockIdx.x;
@@ -1468,13 +1460,22 @@ __global__ void __launch_bounds__(SCAN_T) k_scan_apply(Src src, Work wk) {
     v[k] = e < n ? (u32)wk.cgrid[d.c0 + e] : 0u;
     sum += v[k];
   }
+  // ids before this block: the totals of the image's earlier blocks (a few
+  // thousand at most per image, summed here rather than scanned by a kernel
+  // of their own)
+  u32 part = 0;
+  for (int64_t b = d.blk0 + threadIdx.x; b < gb; b += SCAN_T) part += (u32)wk.bsum[b];
+  u32 before;
+  (void)block_excl_scan(part, tmp, before);
   u32 tot;
-  u32 ex = block_excl_scan(sum, tmp, tot) + (u32)wk.bsum[gb] + 1u;
+  u32 ex = block_excl_scan(sum, tmp, tot) + before + 1u;
   for (int k = 0; k < 4; k++) {
     int64_t e = b0 + threadIdx.x * 4 + k;
     if (e < n) wk.cgrid[d.c0 + e] = (int32_t)ex;
     ex += v[k];
   }
+  // the image's last block knows the number of labels (exterior included)
+  if (threadIdx.x == 0 && gb == d.blk0 + d.nblk - 1 && d.counts) d.counts[0] = 1 + (int64_t)before + (int64_t)tot;
 }
 
 // ---------------------------------------------------------------------------
@@ -1987,7 +1988,7 @@ inline void place_image(ImgDesc& d, int64_t& tiles, int64_t& nodes, int64_t& cel
 // global atomics per node.
 template <class T, bool HASH, class Src, class Launcher>
 inline void enqueue(Launcher& L, const Src& src, const Work& wk, int64_t tiles, int64_t items, int64_t blocks,
-                    int64_t nimages, int64_t supers) {
+                    int64_t supers) {
   L.launch(k_tile_export<T, Src>, tiles, T::NT, src, wk);
   L.launch(k_seam_local<T, Src>, supers, 256, src, wk);
   if (items > 0) L.launch(k_border_merge<T, Src>, (items + 255) / 256, 256, src, wk, items);
@@ -1995,7 +1996,6 @@ inline void enqueue(Launcher& L, const Src& src, const Work& wk, int64_t tiles, 
   else L.launch(k_reduce_direct<T, Src>, tiles, 64, src, wk);
   L.launch(k_leaders<T, Src>, tiles, 64, src, wk);
   L.launch(k_scan_reduce<Src>, blocks, SCAN_T, src, wk);
-  L.launch(k_scan_blocks<Src>, nimages, SCAN_T, src, wk);
   L.launch(k_scan_apply<Src>, blocks, SCAN_T, src, wk);
   L.launch(k_emit_border<T, Src>, tiles, 64, src, wk);
   L.launch(k_node_canon<T, Src>, (tiles * T::BCAP + 255) / 256, 256, src, wk, tiles * T::BCAP);

@@ -25,7 +25,7 @@ import subprocess
 import sys
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
-KERNELS = ["k_tile_export", "k_seam_local", "k_border_merge", "k_reduce_roots", "k_leaders", "k_scan_reduce", "k_scan_blocks",
+KERNELS = ["k_tile_export", "k_seam_local", "k_border_merge", "k_reduce_roots", "k_leaders", "k_scan_reduce",
            "k_scan_apply", "k_emit_border", "k_node_canon", "k_tile_emit"]
 PASSES = {
     "pmc1": ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR",

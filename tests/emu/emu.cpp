@@ -255,11 +255,11 @@ void run_images(std::vector<Image>& ims, bool batch) {
     ccl::Work wk = ccl::make_work(lay, ws.data());
     if (ds.size() == 1 && !batch) {
       ccl::OneImage src{ds[0]};
-      ccl::enqueue<T, true>(L, src, wk, tiles, items, blocks, 1, supers);
+      ccl::enqueue<T, true>(L, src, wk, tiles, items, blocks, supers);
     } else {
       ccl::ManyImages src{ds.data(), (int32_t)ds.size()};
-      if (tiles % 2) ccl::enqueue<T, false>(L, src, wk, tiles, items, blocks, (int64_t)ds.size(), supers);
-      else ccl::enqueue<T, true>(L, src, wk, tiles, items, blocks, (int64_t)ds.size(), supers);
+      if (tiles % 2) ccl::enqueue<T, false>(L, src, wk, tiles, items, blocks, supers);
+      else ccl::enqueue<T, true>(L, src, wk, tiles, items, blocks, supers);
     }
   };
   if (batch) {
