@@ -20,7 +20,9 @@ algorithmic bytes per launch / its average duration, against 8 TB/s.
 `traffic` is the kernel's measured HBM bytes per launch from the committed
 rocprofv3 counter summary (profiles/traffic.json, FETCH_SIZE and WRITE_SIZE
 scaled by a plain copy's readings) when that summary was taken from the
-current kernel sources, else null.
+current kernel sources, else null; `traffic_frac` is that measured traffic
+over the kernel's average duration, against 8 TB/s.  `hbm_copy_ceiling` is
+the best rate of a plain 1 GiB device-to-device copy on the same GPU.
 """
 from __future__ import annotations
 
@@ -195,9 +197,32 @@ def roofline(r, workload: str):
     k = max(r["kernel_avg_ms"], key=r["kernel_avg_ms"].get)
     ms = r["kernel_avg_ms"][k]
     gbs = r["kernel_alg_bytes"][k] / (ms / 1e3) / 1e9
-    return {"bound": "hbm", "kernel": k, "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(workload, k),
-            "alg_bytes_per_launch": int(r["kernel_alg_bytes"][k]), "avg_ms": round(ms, 5)}
+    traffic = measured_traffic(workload, k)
+    out = {"bound": "hbm", "kernel": k, "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+           "alg_bytes_per_launch": int(r["kernel_alg_bytes"][k]), "avg_ms": round(ms, 5)}
+    if traffic is not None:  # measured HBM bytes over the same duration
+        out["traffic_frac"] = round(traffic / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+    return out
+
+
+def copy_ceiling(mib: int = 1024, reps: int = 5):
+    """Best device-to-device copy rate (read + write bytes / time) on this GPU."""
+    import torch
+    n = mib << 20
+    a = torch.empty(n, dtype=torch.uint8, device="cuda:0").fill_(1)
+    b = torch.empty_like(a)
+    best = float("inf")
+    for _ in range(reps + 1):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    del a, b
+    gbs = 2 * n / (best / 1e3) / 1e9
+    return {"GBs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4), "bytes_copied": n}
 
 
 def run_batch(n_images: int, steps: int, warmup: int):
@@ -385,6 +410,7 @@ def main():
                    "shape": list(work[0][1].shape), "tile": list(__import__("paper_2006_09299_amd").tile_shape())},
         "roofline": roofline(r, args.workload),
         "path_hbm": {"alg_GBs": round(path_gbs, 1), "frac": round(path_gbs / HBM_PEAK_GBS, 4)},
+        "hbm_copy_ceiling": copy_ceiling(),
         "kernel_avg_ms": {k: round(v, 5) for k, v in r["kernel_avg_ms"].items()},
     }
     if args.workload == "sweep8192" and not args.no_also:
@@ -406,7 +432,11 @@ def main():
         say(f"  serve: {json.dumps(sv)}")
         sv1 = run_serve(min(args.serve_requests, 4000), batched=False)
         say(f"  serve, one request per launch: {json.dumps(sv1)}")
-        out.setdefault("also", {})["serve"] = {"continuous_batching": sv, "one_request_per_launch": sv1}
+        # offered load far above what one GPU can take: the server's capacity
+        sv2 = run_serve(args.serve_requests, rate_hz=40000.0, warmup_s=0.05)
+        say(f"  serve, overloaded: {json.dumps(sv2)}")
+        out.setdefault("also", {})["serve"] = {"continuous_batching": sv, "one_request_per_launch": sv1,
+                                               "overloaded_40k_req_s": sv2}
     if not args.no_cpu_baseline:
         say("bench: cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(work)

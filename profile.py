@@ -33,7 +33,7 @@ PASSES = {
     "pmc2": ["SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_ANY", "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_VALU",
              "SQ_ACTIVE_INST_LDS", "SQ_WAIT_INST_LDS"],
     "pmc3": ["SQ_LDS_BANK_CONFLICT", "SQ_LDS_IDX_ACTIVE", "SQ_INSTS_LDS_ATOMIC", "FETCH_SIZE"],
-    "pmc4": ["WRITE_SIZE", "SQ_INST_LEVEL_VMEM"],
+    "pmc4": ["WRITE_SIZE", "TCC_ATOMIC_sum", "SQ_INST_LEVEL_VMEM"],
 }
 COPY_MIB = 1024
 
@@ -141,8 +141,8 @@ def summary(workload: str, outdir: str, copydir: str, md: str):
     lines += ["(OUTDIR is made absolute before the runs.)", "", f"Copy calibration ({COPY_MIB} MiB device-to-device): FETCH_SIZE reads {fetch_kib:.0f} KiB "
               f"(scale {f_scale:.3f}), WRITE_SIZE reads {write_kib:.0f} KiB (scale {w_scale:.3f}).", "",
               "Per dispatch averages (every dispatch of the profiled run: warm-up and timed steps):", "",
-              "| kernel | dispatches | avg us | HBM read MB | HBM write MB | VALU/wave | LDS/wave | wait % | LDS bank-conflict % | LDS atomics/wave |",
-              "|---|---|---|---|---|---|---|---|---|---|"]
+              "| kernel | dispatches | avg us | HBM read MB | HBM write MB | VALU/wave | LDS/wave | wait % | LDS bank-conflict % | LDS atomics/wave | L2 atomics/launch |",
+              "|---|---|---|---|---|---|---|---|---|---|---|"]
     traffic = {}
     for k in KERNELS:
         if k not in dur and k not in cnt:
@@ -157,7 +157,7 @@ def summary(workload: str, outdir: str, copydir: str, md: str):
                      f"{avg(k, 'SQ_INSTS_VALU') / waves:.0f} | {avg(k, 'SQ_INSTS_LDS') / waves:.0f} | "
                      f"{100 * avg(k, 'SQ_WAIT_ANY') / avg(k, 'SQ_WAVE_CYCLES'):.0f} | "
                      f"{100 * avg(k, 'SQ_LDS_BANK_CONFLICT') / max(avg(k, 'SQ_LDS_IDX_ACTIVE'), 1):.0f} | "
-                     f"{avg(k, 'SQ_INSTS_LDS_ATOMIC') / waves:.1f} |")
+                     f"{avg(k, 'SQ_INSTS_LDS_ATOMIC') / waves:.1f} | {avg(k, 'TCC_ATOMIC_sum'):.0f} |")
     with open(md, "w") as f:
         f.write("\n".join(lines) + "\n")
     tj = os.path.join(ROOT, "profiles", "traffic.json")
