@@ -105,8 +105,9 @@ const char *ccl_kernel_name(int k);
  * two ways of summing the partial features of components that cross tiles
  * (an LDS hash table per group of tiles, or direct global atomics).  All
  * variants give identical results; they differ in speed per workload.
- * Variant 0 (64 x 128 tiles, 512 threads, LDS hash) is the default of
- * ccl_label. */
+ * Variant 0 (64 x 128 tiles, 256 threads, LDS hash) is the default of
+ * ccl_label.  For tiles of 8192 pixels or more the relabeling kernel
+ * (k_tile_emit) always runs 512 threads per tile. */
 
 /* [host] Number of compiled variants. */
 int32_t ccl_num_variants(void);

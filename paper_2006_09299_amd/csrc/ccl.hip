@@ -28,11 +28,11 @@ constexpr int NVARIANTS = 8;
 template <class F>
 int with_variant(int v, F&& f) {
   switch (v) {
-    case 0: return f(V<64, 128, true, 512>{});
+    case 0: return f(V<64, 128, true>{});
     case 1: return f(V<32, 128, false>{});
     case 2: return f(V<16, 128, true>{});
     case 3: return f(V<32, 256, true, 512>{});
-    case 4: return f(V<64, 128, true>{});
+    case 4: return f(V<64, 128, true, 512>{});
     case 5: return f(V<32, 128, true>{});
     case 6: return f(V<16, 256, true>{});
     case 7: return f(V<32, 256, true>{});

@@ -1999,7 +1999,12 @@ inline void enqueue(Launcher& L, const Src& src, const Work& wk, int64_t tiles, 
   L.launch(k_scan_apply<Src>, blocks, SCAN_T, src, wk);
   L.launch(k_emit_border<T, Src>, tiles, 64, src, wk);
   L.launch(k_node_canon<T, Src>, (tiles * T::BCAP + 255) / 256, 256, src, wk, tiles * T::BCAP);
-  L.launch(k_tile_emit<T, Src>, tiles, T::NT, src, wk);
+  // The relabeling of tiles of 8192 pixels or more runs with 512 threads
+  // whatever the other kernels use: it is bound by memory latency and its
+  // LDS (not wave slots) limits the workgroups per CU, so wider workgroups
+  // keep more waves in flight (measured: faster than 256 and than 1024).
+  using TE = Tile<T::TH, T::TW, (T::N >= 8192 && T::NT < 512 ? 512 : T::NT)>;
+  L.launch(k_tile_emit<TE, Src>, tiles, TE::NT, src, wk);
 }
 
 }  // namespace ccl

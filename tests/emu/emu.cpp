@@ -310,6 +310,7 @@ int main(int argc, char** argv) {
     case 4: run_images<ccl::Tile<64, 64>>(ims, batch); break;
     case 5: run_images<ccl::Tile<1, 64>>(ims, batch); break;
     case 6: run_images<ccl::Tile<16, 128, 512>>(ims, batch); break;
+    case 7: run_images<ccl::Tile<64, 128>>(ims, batch); break;  // relabeling with 512 threads
     default: fprintf(stderr, "bad tile config\n"); return 2;
   }
   FILE* fo = fopen(argv[4], "wb");

@@ -35,7 +35,7 @@ def _cases(seed, n, hmax, wmax):
     return out
 
 
-@pytest.mark.parametrize("cfg", [1, 2, 3, 4, 6])
+@pytest.mark.parametrize("cfg", [1, 2, 3, 4, 6, 7])
 def test_emulated_kernels_small_tiles(cfg):
     imgs = _cases(100 + cfg, 8, 40, 300)
     for img, r in zip(imgs, emu_runner.run(imgs, tile_cfg=cfg)):
