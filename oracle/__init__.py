@@ -130,3 +130,22 @@ def label(img: np.ndarray, lib=None) -> Result:
         color=color[:n].copy(),
         euler=int(euler[0]),
     )
+
+
+def fill_holes(img: np.ndarray, lib=None):
+    """Hole filling, the optional step of the transitive closure (Sec. 3.2,
+    Algorithm 3; Fig. 2, "hole filled"): a component whose surrounding is
+    not the exterior is merged into it, so every hole, with everything
+    nested inside it, joins the top-level foreground component around it.
+
+    Written as the plain definition it reaches: the filled image is the
+    complement of the exterior (the background connected to the image
+    frame), labeled like any image.  Returns (filled Result, map) where
+    map[c] is the filled id of the original component c (the filled label at
+    c's first pixel; the exterior keeps 0)."""
+    r = label(img, lib)
+    f = label((r.labels != 0).astype(np.uint8), lib)
+    mp = np.zeros(r.n_labels, dtype=np.int32)
+    ids, first = np.unique(r.labels.ravel(), return_index=True)  # first pixel of each id in raster order
+    mp[ids] = f.labels.ravel()[first]
+    return f, mp

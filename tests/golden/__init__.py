@@ -31,3 +31,8 @@ def fig2():
     final = [tuple(int(v) for v in r.split()) for r in s["final"]]
     classes = [tuple(int(v) for v in r.split()) for r in s["classes"]]
     return img, prov, new, equiv, final, classes
+
+
+def fig2_filled_classes():
+    s = read_sections("fig2_example.txt")
+    return [tuple(int(v) for v in r.split()) for r in s["filled_classes"]]

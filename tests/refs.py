@@ -19,7 +19,8 @@ None of these share code with ``oracle/`` or with the HIP library:
   oracle also takes (virtual background row above row 0 that belongs to the
   exterior, background runs of the last row attached to the exterior).  It
   also records the events of the scan (new labels with their initial
-  adjacency, equivalences) so the Fig. 2 narrative can be checked.
+  adjacency, equivalences) so the Fig. 2 narrative can be checked, and can
+  take the closure's optional hole-filling step.
 """
 from __future__ import annotations
 
@@ -182,8 +183,13 @@ def _merge_features(f, g):
             f[4] + g[4], f[5] + g[5], f[6] + g[6]]
 
 
-def lsl_bw(img: np.ndarray, fix_bottom: bool = True):
+def lsl_bw(img: np.ndarray, fix_bottom: bool = True, fill_holes: bool = False):
     """Returns (final_labels_per_pixel, T, I, events, F, rows).
+
+    fill_holes: the closure's optional step (Algorithm 3): a root whose
+    surrounding's final label is not the exterior is merged into that
+    surrounding before the closure continues, so nested levels cascade into
+    the top-level foreground.
 
     events: list of ("new", row, label, colour, surrounding) and
     ("equiv", row, kept, merged) in scan order; labels are provisional.
@@ -264,6 +270,8 @@ def lsl_bw(img: np.ndarray, fix_bottom: bool = True):
     # forward transitive closure; roots point their adjacency at a root
     for e in range(1, len(T)):
         a = T[e]
+        if fill_holes and a == e and T[I[e]] > 0:
+            a = T[e] = I[e]
         if a < e:
             T[e] = T[a]
             if F[e] is not None:
