@@ -143,6 +143,33 @@ int ccl_batch_prepare(const ccl_image_t *imgs, int32_t n, int32_t variant, void 
 int ccl_label_batch(const ccl_image_t *imgs, int32_t n, int32_t variant, const void *dev_desc, void *ws,
                     size_t ws_bytes, void *stream);
 
+/* Hole filling (Sec. 3.2, the transitive closure's optional step in
+ * Algorithm 3; Fig. 2, "hole filled"): a component whose surrounding is not
+ * the exterior is merged into it, so every hole, with everything nested in
+ * it, joins the top-level foreground component around it.  The result is the
+ * labeling of the filled image (the complement of the exterior): the exterior
+ * (id 0, unchanged) and the top-level foreground components, with canonical
+ * ids (raster rank of the first pixel), merged S/Sx/Sy, their own bounding
+ * boxes, parent 0, colour 1, and counts = {number of filled labels, Euler
+ * number = number of filled foreground components}.
+ *
+ * `in`: the outputs of ccl_label / ccl_label_batch for a w x h image, on the
+ * device (parent and counts required; labels / features when the filled
+ * ones are asked for); the number of labels is read from in->counts[0] on
+ * the device, so no synchronisation is needed between the two calls.  If
+ * that labeling's tables were truncated (counts[0] > cap), out->counts[0] is
+ * set to -1 and nothing else is written.
+ * `out`: filled labels [w*h] (row stride w), features, parent, colour
+ * [out->cap] (each may be NULL) and counts [2]; as for ccl_label, entries
+ * with id >= out->cap are dropped while counts[0] stays true.  The number of
+ * filled labels never exceeds the number of labels.
+ * `map` [in->cap] (device, may be NULL): filled id of every original id.
+ * `ws` [ccl_fill_workspace_bytes(in->cap)] scratch, no initialisation.
+ * Errors as for ccl_label (CCL_EINVAL, CCL_ENOSPC, CCL_EHIP), on the host. */
+size_t ccl_fill_workspace_bytes(int64_t cap);
+int ccl_fill_holes(const ccl_outputs_t *in, int32_t w, int32_t h, const ccl_outputs_t *out, int32_t *map, void *ws,
+                   size_t ws_bytes, void *stream);
+
 /* Serving: continuous batching over ccl_label_batch.  The paper labels one
  * image at a time; this front end runs the same path for a stream of requests
  * of any sizes.  Requests are admitted in arrival order as soon as a slot and

@@ -117,4 +117,50 @@ def label(img: torch.Tensor, cap: Optional[int] = None, labels: bool = True, var
     return Result(buf.labels, buf.features[:n], buf.parent[:n], buf.color[:n], n, euler)
 
 
+def fill_holes(res: Result, shape=None, labels: bool = True, return_map: bool = False, stream: Optional[int] = None):
+    """Hole filling on a finished labeling (ccl_fill_holes): every hole, with
+    everything nested in it, joins the top-level foreground component around
+    it.  `res` is a Result of label() / label_batch(); `shape` (h, w) is
+    needed only when res has no label image.  Returns the filled image's
+    Result (and, with return_map, the filled id of every original id);
+    synchronises to read the number of filled labels."""
+    if res.labels is not None:
+        h, w = res.labels.shape
+    elif shape is None:
+        raise ValueError("fill_holes needs shape=(h, w) for a result without a label image")
+    else:
+        h, w = shape
+    dev = res.parent.device
+    n = int(res.n_labels)
+    for t in (res.features, res.parent, res.color) + ((res.labels,) if res.labels is not None else ()):
+        if not t.is_contiguous():
+            raise ValueError("fill_holes expects the contiguous tables of a labeling")
+    want_labels = labels and res.labels is not None
+    counts_in = torch.tensor([n, int(res.euler)], dtype=torch.int64, device=dev)
+    inp = _capi.ccl_outputs_t(res.labels.data_ptr() if res.labels is not None else None, res.features.data_ptr(),
+                              res.parent.data_ptr(), res.color.data_ptr(), n, counts_in.data_ptr())
+    olabels = torch.empty((h, w), dtype=torch.int32, device=dev) if want_labels else None
+    ofeat = torch.empty((n, 5), dtype=torch.int64, device=dev)
+    oparent = torch.empty(n, dtype=torch.int32, device=dev)
+    ocolor = torch.empty(n, dtype=torch.uint8, device=dev)
+    ocounts = torch.zeros(2, dtype=torch.int64, device=dev)
+    out = _capi.ccl_outputs_t(olabels.data_ptr() if want_labels else None, ofeat.data_ptr(), oparent.data_ptr(),
+                              ocolor.data_ptr(), n, ocounts.data_ptr())
+    mp = torch.empty(n, dtype=torch.int32, device=dev) if return_map else None
+    wsb = int(_capi.lib().ccl_fill_workspace_bytes(n))
+    ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev).cuda_stream
+    rc = _capi.lib().ccl_fill_holes(ctypes.byref(inp), int(w), int(h), ctypes.byref(out),
+                                    ctypes.c_void_p(mp.data_ptr()) if mp is not None else None,
+                                    ctypes.c_void_p(ws.data_ptr()), wsb, ctypes.c_void_p(stream))
+    _capi.check(rc, "ccl_fill_holes")
+    c = ocounts.cpu()
+    nf, eu = int(c[0]), int(c[1])
+    if nf < 0:
+        raise _capi.CclError(_capi.CCL_ECAPACITY, "ccl_fill_holes (the labeling's tables were truncated)")
+    filled = Result(olabels, ofeat[:nf], oparent[:nf], ocolor[:nf], nf, eu)
+    return (filled, mp) if return_map else filled
+
+
 from .batch import BatchPlan, label_batch  # noqa: E402,F401

@@ -70,6 +70,7 @@ EXPORTS = (
     "ccl_variant_info", "ccl_workspace_bytes_v", "ccl_label_v", "ccl_batch_sizes", "ccl_batch_prepare",
     "ccl_label_batch", "ccl_strerror", "ccl_tile_shape", "ccl_server_create", "ccl_server_footprint",
     "ccl_server_submit", "ccl_server_poll", "ccl_server_release", "ccl_server_stats", "ccl_server_destroy",
+    "ccl_fill_workspace_bytes", "ccl_fill_holes",
 )
 TRACE_EVENTS = 11
 
@@ -139,6 +140,11 @@ def lib():
         L.ccl_server_stats.argtypes = [vp, ctypes.POINTER(ccl_server_stats_t)]
         L.ccl_server_destroy.restype = ctypes.c_int
         L.ccl_server_destroy.argtypes = [vp]
+        L.ccl_fill_workspace_bytes.restype = ctypes.c_size_t
+        L.ccl_fill_workspace_bytes.argtypes = [i64]
+        L.ccl_fill_holes.restype = ctypes.c_int
+        L.ccl_fill_holes.argtypes = [ctypes.POINTER(ccl_outputs_t), i32, i32, ctypes.POINTER(ccl_outputs_t), vp, vp,
+                                     ctypes.c_size_t, vp]
         L.ccl_tile_shape.restype = None
         L.ccl_tile_shape.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
         _lib = L

@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include "ccl_pipeline.h"
+#include "ccl_fill.h"
 #include "../../include/ccl.h"
 
 namespace {
@@ -124,9 +125,79 @@ int label_one(const uint8_t* img, int32_t w, int32_t h, int64_t pitch, const ccl
   });
 }
 
+// workspace of the hole filling: top-level ancestor, filled id and map per
+// table entry, block counts
+struct FillLayout {
+  int64_t nblk;
+  size_t off_top, off_fid, off_map, off_bsum, bytes;
+};
+
+FillLayout fill_layout(int64_t cap) {
+  auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  FillLayout L;
+  L.nblk = (cap + ccl::fill::FB - 1) / ccl::fill::FB;
+  size_t o = 0;
+  L.off_top = o;
+  o += al(4 * (size_t)cap);
+  L.off_fid = o;
+  o += al(4 * (size_t)cap);
+  L.off_map = o;
+  o += al(4 * (size_t)cap);
+  L.off_bsum = o;
+  o += al(4 * (size_t)L.nblk);
+  L.bytes = o;
+  return L;
+}
+
 }  // namespace
 
 extern "C" {
+
+size_t ccl_fill_workspace_bytes(int64_t cap) {
+  if (cap < 1 || cap >= INT32_MAX) return 0;
+  return fill_layout(cap).bytes;
+}
+
+int ccl_fill_holes(const ccl_outputs_t* in, int32_t w, int32_t h, const ccl_outputs_t* out, int32_t* map, void* ws,
+                   size_t ws_bytes, void* stream) {
+  if (!in || !out || !ws || !in->parent || !in->counts || !out->counts) return CCL_EINVAL;
+  if (in->cap < 1 || in->cap >= INT32_MAX || w <= 0 || h <= 0 || (int64_t)w * h >= INT32_MAX) return CCL_EINVAL;
+  if ((out->labels && !in->labels) || (out->features && !in->features)) return CCL_EINVAL;
+  if ((out->features || out->parent || out->color) && out->cap < 1) return CCL_EINVAL;
+  const FillLayout L = fill_layout(in->cap);
+  if (ws_bytes < L.bytes) return CCL_ENOSPC;
+  uint8_t* b = static_cast<uint8_t*>(ws);
+  ccl::fill::Args a;
+  a.labels = in->labels;
+  a.feat = reinterpret_cast<const ccl::Feature*>(in->features);
+  a.parent = in->parent;
+  a.counts = in->counts;
+  a.cap = in->cap;
+  a.npx = (int64_t)w * h;
+  a.olabels = out->labels;
+  a.ofeat = reinterpret_cast<ccl::Feature*>(out->features);
+  a.oparent = out->parent;
+  a.ocolor = out->color;
+  a.ocap = out->cap;
+  a.ocounts = out->counts;
+  a.top = reinterpret_cast<int32_t*>(b + L.off_top);
+  a.fid = reinterpret_cast<int32_t*>(b + L.off_fid);
+  a.map = map ? map : reinterpret_cast<int32_t*>(b + L.off_map);
+  a.bsum = reinterpret_cast<int32_t*>(b + L.off_bsum);
+  a.nblk = L.nblk;
+  using namespace ccl::fill;
+  HipLauncher hl{static_cast<hipStream_t>(stream)};
+  hl.launch(k_fill_top, L.nblk, FT, a);
+  hl.launch(k_fill_scan, 1, SCAN_WG, a);
+  hl.launch(k_fill_ids, L.nblk, FT, a);
+  hl.launch(k_fill_merge, L.nblk, FT, a);
+  if (out->labels) {
+    int64_t blocks = (a.npx / 4 + FT - 1) / FT;
+    blocks = blocks < 1 ? 1 : (blocks > 16384 ? 16384 : blocks);
+    hl.launch(k_fill_labels, blocks, FT, a);
+  }
+  return hl.err == hipSuccess ? CCL_OK : CCL_EHIP;
+}
 
 int32_t ccl_num_variants(void) { return NVARIANTS; }
 

@@ -1,0 +1,240 @@
+// ccl_fill.h -- hole filling on a finished labeling (gfx950).
+//
+// The transitive closure of the paper has an optional step (Sec. 3.2,
+// Algorithm 3; Fig. 2, "hole filled"): a component whose surrounding is not
+// the exterior is merged into that surrounding, and since the closure runs
+// forward, nested levels cascade into the top-level foreground component.
+// With the inclusion tree at hand (parent table of the labeling) that is:
+// the filled component of c is its top-level ancestor t (parent[t] = exterior),
+// the filled image's components are the exterior and the top-level foreground
+// components, each with everything nested inside it.
+//
+// Filled ids keep the canonical rule (exterior 0, others by the raster rank
+// of their first pixel): a top-level component's first pixel is also the
+// first pixel of its filled region (what it encloses lies below or right of
+// it), so the filled id of t is 1 + the number of top-level ids below t.
+// Features: S, Sx, Sy of the nested components are added; the bounding box is
+// the top-level component's own (an enclosed pixel lies between pixels of its
+// surrounding in its row and in its column).
+//
+// Kernels, one launch each, in this order:
+//   k_fill_top    : top-level ancestor of every id (walk up the parent table,
+//                   whose entries strictly decrease); top-level ids per block
+//   k_fill_scan   : one workgroup: exclusive scan of the block counts; the
+//                   filled counts and the exterior's table entries
+//   k_fill_ids    : filled id of every top-level id, its table entries
+//   k_fill_merge  : filled id of every id (map); S, Sx, Sy of nested ids
+//                   added into their filled component
+//   k_fill_labels : filled label image = map[label] (optional)
+// The number of labels is read on the device (counts[0] of the labeling), so
+// the sequence needs no host synchronisation; grids cover the table capacity.
+#pragma once
+
+#include <stdint.h>
+
+namespace ccl {
+namespace fill {
+
+constexpr int FT = 256;       // threads per workgroup
+constexpr int FK = 4;         // ids per thread
+constexpr int FB = FT * FK;   // ids per block
+constexpr int SCAN_WG = 1024; // threads of the block-count scan
+
+struct Args {
+  // the labeling (device)
+  const int32_t* labels;   // [npx] or null
+  const Feature* feat;     // [cap] or null
+  const int32_t* parent;   // [cap]
+  const int64_t* counts;   // [2]
+  int64_t cap;
+  int64_t npx;
+  // the filled labeling (device)
+  int32_t* olabels;        // [npx] or null
+  Feature* ofeat;          // [ocap] or null
+  int32_t* oparent;        // [ocap] or null
+  uint8_t* ocolor;         // [ocap] or null
+  int64_t ocap;
+  int64_t* ocounts;        // [2]
+  // scratch (device)
+  int32_t* map;            // [cap]: filled id of every id
+  int32_t* top;            // [cap]: top-level ancestor
+  int32_t* fid;            // [cap]: filled id, at top-level ids
+  int32_t* bsum;           // [nblk]: top-level ids per block, then block offsets
+  int64_t nblk;
+};
+
+// the labeling is usable: 1 <= n <= cap (a truncated labeling has n > cap)
+__device__ inline int64_t fill_n(const Args& a) {
+  const int64_t n = a.counts[0];
+  return n >= 1 && n <= a.cap ? n : 0;
+}
+
+__device__ inline bool is_top(const Args& a, int64_t c) { return c > 0 && a.parent[c] == 0; }
+
+// workgroup-wide exclusive sum of v over FT threads (total in *tot)
+__device__ inline uint32_t fill_block_scan(uint32_t v, uint32_t* tmp, uint32_t* tot) {
+  const int t = threadIdx.x;
+  tmp[t] = v;
+  __syncthreads();
+  for (int d = 1; d < FT; d <<= 1) {
+    uint32_t add = t >= d ? tmp[t - d] : 0u;
+    __syncthreads();
+    tmp[t] += add;
+    __syncthreads();
+  }
+  *tot = tmp[FT - 1];
+  const uint32_t ex = tmp[t] - v;
+  __syncthreads();
+  return ex;
+}
+
+__global__ void __launch_bounds__(FT) k_fill_top(Args a) {
+  __shared__ uint32_t tmp[FT];
+  const int64_t n = fill_n(a);
+  const int64_t c0 = (int64_t)blockIdx.x * FB + (int64_t)threadIdx.x * FK;
+  uint32_t cnt = 0;
+  for (int k = 0; k < FK; k++) {
+    const int64_t c = c0 + k;
+    if (c >= n) break;
+    // walk up; parent entries strictly decrease down to the exterior, so
+    // the walk ends (an entry that does not decrease stops it)
+    int32_t t = (int32_t)c;
+    if (c > 0) {
+      int32_t p = a.parent[t];
+      while (p > 0 && p < t) {
+        t = p;
+        p = a.parent[t];
+      }
+    }
+    a.top[c] = t;
+    cnt += is_top(a, c) ? 1u : 0u;
+  }
+  uint32_t tot;
+  (void)fill_block_scan(cnt, tmp, &tot);
+  if (threadIdx.x == 0 && (int64_t)blockIdx.x < a.nblk) a.bsum[blockIdx.x] = (int32_t)tot;
+}
+
+__global__ void __launch_bounds__(SCAN_WG) k_fill_scan(Args a) {
+  __shared__ uint32_t tmp[SCAN_WG];
+  const int t = threadIdx.x;
+  const int64_t n = fill_n(a);
+  const int64_t nb = n ? (n + FB - 1) / FB : 0;
+  uint32_t carry = 0;
+  for (int64_t base = 0; base < nb; base += SCAN_WG) {
+    const int64_t b = base + t;
+    const uint32_t v = b < nb ? (uint32_t)a.bsum[b] : 0u;
+    tmp[t] = v;
+    __syncthreads();
+    for (int d = 1; d < SCAN_WG; d <<= 1) {
+      uint32_t add = t >= d ? tmp[t - d] : 0u;
+      __syncthreads();
+      tmp[t] += add;
+      __syncthreads();
+    }
+    if (b < nb) a.bsum[b] = (int32_t)(carry + tmp[t] - v);
+    carry += tmp[SCAN_WG - 1];
+    __syncthreads();
+  }
+  if (t == 0) {
+    if (!n) {  // the labeling's tables were truncated: nothing is filled
+      a.ocounts[0] = -1;
+      a.ocounts[1] = 0;
+      return;
+    }
+    a.ocounts[0] = 1 + (int64_t)carry;  // the exterior and the top-level components
+    a.ocounts[1] = (int64_t)carry;      // no holes are left
+    if (a.ocap >= 1) {
+      if (a.ofeat && a.feat) a.ofeat[0] = a.feat[0];  // the exterior does not change
+      if (a.oparent) a.oparent[0] = -1;
+      if (a.ocolor) a.ocolor[0] = 0;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(FT) k_fill_ids(Args a) {
+  __shared__ uint32_t tmp[FT];
+  const int64_t n = fill_n(a);
+  const int64_t c0 = (int64_t)blockIdx.x * FB + (int64_t)threadIdx.x * FK;
+  uint32_t cnt = 0;
+  for (int k = 0; k < FK; k++) {
+    const int64_t c = c0 + k;
+    if (c < n && is_top(a, c)) cnt++;
+  }
+  uint32_t tot;
+  uint32_t f = fill_block_scan(cnt, tmp, &tot);
+  if (!n || (int64_t)blockIdx.x >= a.nblk) return;
+  f += 1u + (uint32_t)a.bsum[blockIdx.x];
+  for (int k = 0; k < FK; k++) {
+    const int64_t c = c0 + k;
+    if (c >= n || !is_top(a, c)) continue;
+    a.fid[c] = (int32_t)f;
+    if ((int64_t)f < a.ocap) {
+      if (a.ofeat && a.feat) a.ofeat[f] = a.feat[c];
+      if (a.oparent) a.oparent[f] = 0;
+      if (a.ocolor) a.ocolor[f] = 1;
+    }
+    f++;
+  }
+}
+
+__global__ void __launch_bounds__(FT) k_fill_merge(Args a) {
+  const int64_t n = fill_n(a);
+  const int64_t c0 = (int64_t)blockIdx.x * FB + (int64_t)threadIdx.x * FK;
+  for (int k = 0; k < FK; k++) {
+    const int64_t c = c0 + k;
+    if (c >= n) break;
+    const int32_t t = a.top[c];
+    const int32_t f = t > 0 ? a.fid[t] : 0;
+    a.map[c] = f;
+    if (c > 0 && t != c && f > 0 && (int64_t)f < a.ocap && a.ofeat && a.feat) {
+      const Feature& g = a.feat[c];
+      Feature* o = &a.ofeat[f];
+      atomicAdd(reinterpret_cast<unsigned long long*>(&o->S), (unsigned long long)g.S);
+      atomicAdd(reinterpret_cast<unsigned long long*>(&o->Sx), (unsigned long long)g.Sx);
+      atomicAdd(reinterpret_cast<unsigned long long*>(&o->Sy), (unsigned long long)g.Sy);
+    }
+  }
+}
+
+// four pixels per thread and step, grid-stride
+__global__ void __launch_bounds__(FT) k_fill_labels(Args a) {
+  const int64_t n = fill_n(a);
+  if (!n) return;
+  const int64_t nq = a.npx / 4;
+  const bool vec = ((reinterpret_cast<uintptr_t>(a.labels) | reinterpret_cast<uintptr_t>(a.olabels)) & 15) == 0;
+  const int64_t stride = (int64_t)gridDim.x * FT;
+  for (int64_t q = (int64_t)blockIdx.x * FT + threadIdx.x; q < nq; q += stride) {
+    const int64_t i = 4 * q;
+    int32_t v[4];
+    if (vec) {
+      const int4 l = *reinterpret_cast<const int4*>(a.labels + i);
+      v[0] = l.x;
+      v[1] = l.y;
+      v[2] = l.z;
+      v[3] = l.w;
+    } else {
+      for (int k = 0; k < 4; k++) v[k] = a.labels[i + k];
+    }
+    for (int k = 0; k < 4; k++) v[k] = (uint64_t)v[k] < (uint64_t)n ? a.map[v[k]] : -1;
+    if (vec) {
+      int4 o;
+      o.x = v[0];
+      o.y = v[1];
+      o.z = v[2];
+      o.w = v[3];
+      *reinterpret_cast<int4*>(a.olabels + i) = o;
+    } else {
+      for (int k = 0; k < 4; k++) a.olabels[i + k] = v[k];
+    }
+  }
+  // the last npx % 4 pixels
+  const int64_t tail = a.npx - 4 * nq;
+  if (blockIdx.x == 0 && threadIdx.x < tail) {
+    const int64_t i = 4 * nq + threadIdx.x;
+    const int32_t v = a.labels[i];
+    a.olabels[i] = (uint64_t)v < (uint64_t)n ? a.map[v] : -1;
+  }
+}
+
+}  // namespace fill
+}  // namespace ccl

@@ -96,3 +96,29 @@ def test_variants_are_described():
     assert _capi.variant_info(0)[:2] == _capi.tile_shape()
     with pytest.raises(_capi.CclError):
         _capi.variant_info(n)
+
+
+def test_fill_holes_rejects_bad_arguments_on_host():
+    L = _capi.lib()
+    fake = 0x1000  # never dereferenced: every case fails validation first
+    E = _capi.CCL_EINVAL
+    good_in = _capi.ccl_outputs_t(fake, fake, fake, fake, 100, fake)
+    good_out = _capi.ccl_outputs_t(fake, fake, fake, fake, 100, fake)
+    wsb = int(L.ccl_fill_workspace_bytes(100))
+    assert wsb > 0 and L.ccl_fill_workspace_bytes(0) == 0
+
+    def call(i, w, h, o, ws=fake, n=wsb):
+        return L.ccl_fill_holes(ctypes.byref(i) if i is not None else None, w, h,
+                                ctypes.byref(o) if o is not None else None, None, ws, n, None)
+
+    assert call(None, 8, 8, good_out) == E
+    assert call(good_in, 8, 8, None) == E
+    assert call(good_in, 0, 8, good_out) == E
+    assert call(good_in, 65536, 65536, good_out) == E
+    assert call(_capi.ccl_outputs_t(fake, fake, None, fake, 100, fake), 8, 8, good_out) == E  # no parent
+    assert call(_capi.ccl_outputs_t(fake, fake, fake, fake, 100, None), 8, 8, good_out) == E  # no counts
+    assert call(_capi.ccl_outputs_t(None, fake, fake, fake, 100, fake), 8, 8, good_out) == E  # labels asked, none given
+    assert call(_capi.ccl_outputs_t(fake, None, fake, fake, 100, fake), 8, 8, good_out) == E  # features likewise
+    assert call(good_in, 8, 8, _capi.ccl_outputs_t(fake, fake, fake, fake, 0, fake)) == E
+    assert call(good_in, 8, 8, good_out, ws=None) == E
+    assert call(good_in, 8, 8, good_out, n=wsb - 1) == _capi.CCL_ENOSPC
