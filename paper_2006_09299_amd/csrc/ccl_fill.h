@@ -177,23 +177,87 @@ __global__ void __launch_bounds__(FT) k_fill_ids(Args a) {
   }
 }
 
+__device__ inline unsigned long long fill_wave_sum(unsigned long long v) {
+  for (int o = 32; o; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ inline void fill_add(Feature* o, unsigned long long s0, unsigned long long s1, unsigned long long s2) {
+  atomicAdd(reinterpret_cast<unsigned long long*>(&o->S), s0);
+  atomicAdd(reinterpret_cast<unsigned long long*>(&o->Sx), s1);
+  atomicAdd(reinterpret_cast<unsigned long long*>(&o->Sy), s2);
+}
+
+// One id per lane and step (a wave covers 64 consecutive ids per step).  A
+// percolating top-level component can hold millions of nested ids, all
+// adding into the same three counters: the workgroup takes the target of its
+// first contributing id as a candidate, sums every contribution to it (wave
+// reductions, then LDS) and adds once; within a wave, contributions to the
+// target of the wave's first other lane are summed too; the rest add
+// directly.
 __global__ void __launch_bounds__(FT) k_fill_merge(Args a) {
+  __shared__ int32_t wcand[FT / 64];
+  __shared__ unsigned long long bsum3[3];
   const int64_t n = fill_n(a);
-  const int64_t c0 = (int64_t)blockIdx.x * FB + (int64_t)threadIdx.x * FK;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t c0 = (int64_t)blockIdx.x * FB + (int64_t)wave * 64 * FK;
+  int32_t f[FK];
+  bool add[FK];
+  unsigned long long s0[FK], s1[FK], s2[FK];
+  int32_t wc = -1;
+#pragma unroll
   for (int k = 0; k < FK; k++) {
-    const int64_t c = c0 + k;
-    if (c >= n) break;
-    const int32_t t = a.top[c];
-    const int32_t f = t > 0 ? a.fid[t] : 0;
-    a.map[c] = f;
-    if (c > 0 && t != c && f > 0 && (int64_t)f < a.ocap && a.ofeat && a.feat) {
-      const Feature& g = a.feat[c];
-      Feature* o = &a.ofeat[f];
-      atomicAdd(reinterpret_cast<unsigned long long*>(&o->S), (unsigned long long)g.S);
-      atomicAdd(reinterpret_cast<unsigned long long*>(&o->Sx), (unsigned long long)g.Sx);
-      atomicAdd(reinterpret_cast<unsigned long long*>(&o->Sy), (unsigned long long)g.Sy);
+    const int64_t c = c0 + k * 64 + lane;
+    f[k] = 0;
+    add[k] = false;
+    s0[k] = s1[k] = s2[k] = 0;
+    if (c < n) {
+      const int32_t t = a.top[c];
+      f[k] = t > 0 ? a.fid[t] : 0;
+      a.map[c] = f[k];
+      add[k] = c > 0 && t != c && f[k] > 0 && (int64_t)f[k] < a.ocap && a.ofeat && a.feat;
+      if (add[k]) {
+        const Feature& g = a.feat[c];
+        s0[k] = (unsigned long long)g.S;
+        s1[k] = (unsigned long long)g.Sx;
+        s2[k] = (unsigned long long)g.Sy;
+      }
+    }
+    const unsigned long long act = __ballot(add[k]);
+    if (wc < 0 && act) wc = __shfl(f[k], __builtin_ctzll(act), 64);
+  }
+  if (lane == 0) wcand[wave] = wc;
+  if (threadIdx.x < 3) bsum3[threadIdx.x] = 0;
+  __syncthreads();
+  int32_t cand = -1;
+  for (int w = 0; w < FT / 64 && cand < 0; w++) cand = wcand[w];
+  unsigned long long p0 = 0, p1 = 0, p2 = 0;  // this wave's sum for the candidate
+#pragma unroll
+  for (int k = 0; k < FK; k++) {
+    const bool mine = add[k] && f[k] == cand;
+    p0 += fill_wave_sum(mine ? s0[k] : 0ull);
+    p1 += fill_wave_sum(mine ? s1[k] : 0ull);
+    p2 += fill_wave_sum(mine ? s2[k] : 0ull);
+    const bool rest = add[k] && !mine;
+    const unsigned long long act = __ballot(rest);
+    if (act) {
+      const int ll = __builtin_ctzll(act);
+      const int32_t fl = __shfl(f[k], ll, 64);
+      const bool same = rest && f[k] == fl;
+      const unsigned long long t0 = fill_wave_sum(same ? s0[k] : 0ull);
+      const unsigned long long t1 = fill_wave_sum(same ? s1[k] : 0ull);
+      const unsigned long long t2 = fill_wave_sum(same ? s2[k] : 0ull);
+      if (lane == ll) fill_add(&a.ofeat[fl], t0, t1, t2);
+      if (rest && !same) fill_add(&a.ofeat[f[k]], s0[k], s1[k], s2[k]);
     }
   }
+  if (lane == 0 && cand > 0 && (p0 | p1 | p2)) {
+    atomicAdd(&bsum3[0], p0);
+    atomicAdd(&bsum3[1], p1);
+    atomicAdd(&bsum3[2], p2);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && cand > 0 && (bsum3[0] | bsum3[1] | bsum3[2])) fill_add(&a.ofeat[cand], bsum3[0], bsum3[1], bsum3[2]);
 }
 
 // four pixels per thread and step, grid-stride
