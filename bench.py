@@ -337,6 +337,68 @@ def run_serve(n_requests: int, rate_hz: float = 2000.0, warmup_s: float = 1.0, p
             "micro_batches": st.launches, "relaunched": st.relaunched}
 
 
+def run_fill_and_features_only(work, reps: int = 3):
+    """Widened rows of the path, on the same images: hole filling after a
+    labeling (ccl_fill_holes, filled label image and tables), and the
+    features-only mode (ccl_label with no label image).  Per image: label
+    once, then `reps` timed calls (events on the stream the kernels run on)."""
+    import torch
+    import paper_2006_09299_amd as ccl
+    from paper_2006_09299_amd import _capi
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    lib = _capi.lib()
+    h, w = work[0][1].shape
+    buf = ccl.Buffers(w, h, w * h // 4 + 1024, dev)
+    fo = ccl.Buffers(w, h, w * h // 4 + 1024, dev, labels=False)
+    olab = torch.empty((h, w), dtype=torch.int32, device=dev)
+    ofeat = torch.empty((buf.cap, 5), dtype=torch.int64, device=dev)
+    opar = torch.empty(buf.cap, dtype=torch.int32, device=dev)
+    ocol = torch.empty(buf.cap, dtype=torch.uint8, device=dev)
+    oc = torch.zeros(2, dtype=torch.int64, device=dev)
+    out = _capi.ccl_outputs_t(olab.data_ptr(), ofeat.data_ptr(), opar.data_ptr(), ocol.data_ptr(), buf.cap,
+                              oc.data_ptr())
+    wsb = int(lib.ccl_fill_workspace_bytes(buf.cap))
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    fill_ms, fo_ms, label_ms, px, fill_bytes = 0.0, 0.0, 0.0, 0, 0
+    for _, img in work:
+        t = torch.from_numpy(img).to(dev)
+        ccl.launch(t, buf)  # warm
+        ccl.launch(t, fo)
+        torch.cuda.synchronize()
+        n_lab = int(buf.counts[0].item())
+        for _ in range(reps + 1):  # the first of each is a warm-up
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+            e[0].record(stream)
+            ccl.launch(t, buf)
+            e[1].record(stream)
+            e[2].record(stream)
+            rc = lib.ccl_fill_holes(ctypes.byref(buf.out), w, h, ctypes.byref(out), None, ctypes.c_void_p(ws.data_ptr()),
+                                    wsb, ctypes.c_void_p(stream.cuda_stream))
+            _capi.check(rc, "ccl_fill_holes")
+            e[3].record(stream)
+            e[4].record(stream)
+            ccl.launch(t, fo)
+            e[5].record(stream)
+            torch.cuda.synchronize()
+            if _ > 0:
+                label_ms += e[0].elapsed_time(e[1])
+                fill_ms += e[2].elapsed_time(e[3])
+                fo_ms += e[4].elapsed_time(e[5])
+        n_fill = int(oc[0].item())
+        px += w * h * reps
+        # read the label image and the labeling's tables, write the filled ones
+        fill_bytes += reps * (8 * w * h + 45 * n_lab + 45 * n_fill)
+    gps = lambda ms: round(px / (ms / 1e3) / 1e9, 2)
+    fill_gbs = fill_bytes / (fill_ms / 1e3) / 1e9
+    return {"images": len(work), "label_Gpixel_s": gps(label_ms),
+            "fill_holes": {"Gpixel_s": gps(fill_ms), "ms_per_image": round(fill_ms / (px / (w * h)), 4),
+                           "label_plus_fill_Gpixel_s": gps(label_ms + fill_ms),
+                           "alg_GBs": round(fill_gbs, 1), "hbm_frac": round(fill_gbs / HBM_PEAK_GBS, 4)},
+            "features_only": {"Gpixel_s": gps(fo_ms), "ms_per_image": round(fo_ms / (px / (w * h)), 4)}}
+
+
 def cpu_baseline(work, budget_s: float = 15.0):
     """The oracle as it stands, single-threaded, on a bounded sample."""
     import oracle
@@ -368,6 +430,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-also", action="store_true", help="skip the secondary structured16384 measurement")
     ap.add_argument("--serve-requests", type=int, default=20000, help="measured requests of the serving leg")
+    ap.add_argument("--fill-only", action="store_true",
+                    help="only the hole-filling / features-only leg on the sweep images (for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run one plain device-to-device copy of MIB MiB (scales the HBM byte counters)")
     args = ap.parse_args()
@@ -386,6 +450,10 @@ def main():
               "(multi-GPU sharding is a design note, not built); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    if args.fill_only:
+        fx = run_fill_and_features_only(make_workload("sweep8192"), reps=1)
+        print(json.dumps({"fill_and_features_only_sweep8192": fx}), flush=True)
+        return
     say(f"bench: workload {args.workload}, steps {args.steps}, warmup {args.warmup}")
     work = make_workload(args.workload)
     r = run_gpu(work, args.steps, args.warmup)
@@ -423,6 +491,11 @@ def main():
             "path_hbm_frac": round(r2["alg_bytes_per_step"] / (ms2 / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
             "roofline": roofline(r2, "structured16384"),
             "kernel_avg_ms": {k: round(v, 5) for k, v in r2["kernel_avg_ms"].items()}}}
+    if args.workload == "sweep8192" and not args.no_also:
+        say("bench: hole filling and features-only mode on the same images")
+        fx = run_fill_and_features_only(work)
+        say(f"  {json.dumps(fx)}")
+        out.setdefault("also", {})["fill_and_features_only_sweep8192"] = fx
     if args.workload == "sweep8192" and not args.no_also:
         say("bench: secondary workload batch4096")
         out.setdefault("also", {})["batch4096"] = run_batch(4096, max(3, args.steps), 1)

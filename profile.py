@@ -2,6 +2,8 @@
 """rocprofv3 passes over bench.py and their summary (run on an MI355X).
 
   python profile.py run WORKLOAD OUTDIR      kernel trace + counter passes
+        (WORKLOAD: sweep8192, structured16384, or fill_sweep8192 for the
+        hole-filling / features-only leg)
   python profile.py copy OUTDIR              FETCH_SIZE / WRITE_SIZE of a 1 GiB copy
   python profile.py summary WORKLOAD OUTDIR COPYDIR MD
         writes MD (per-kernel durations and counters, markdown) and updates
@@ -26,7 +28,8 @@ import sys
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 KERNELS = ["k_tile_export", "k_seam_local", "k_border_merge", "k_reduce_roots", "k_leaders", "k_scan_reduce",
-           "k_scan_apply", "k_emit_border", "k_node_canon", "k_tile_emit"]
+           "k_scan_apply", "k_emit_border", "k_node_canon", "k_tile_emit", "k_fill_top", "k_fill_scan", "k_fill_ids",
+           "k_fill_merge", "k_fill_labels"]
 PASSES = {
     "pmc1": ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR",
              "SQ_INSTS_BRANCH", "SQ_INSTS_SMEM"],
@@ -39,6 +42,8 @@ COPY_MIB = 1024
 
 
 def _bench_cmd(workload: str):
+    if workload == "fill_sweep8192":  # label, fill holes, features only: once per sweep image after a warm call
+        return ["python3", os.path.join(ROOT, "bench.py"), "--fill-only"]
     return ["python3", os.path.join(ROOT, "bench.py"), "--workload", workload, "--steps", "1", "--warmup", "1",
             "--no-cpu-baseline", "--no-also"]
 
@@ -75,7 +80,7 @@ def copy(outdir: str):
 
 
 def _short(name: str) -> str:
-    m = re.search(r"ccl::(k_\w+)", name)
+    m = re.search(r"ccl::(?:fill::)?(k_\w+)", name)
     return m.group(1) if m else name[:40]
 
 
