@@ -39,14 +39,21 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
+_ARGS = [
+    ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
+    ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+    ctypes.c_void_p, ctypes.c_void_p,
+]
+
+
 def _bind(lib):
     f = lib.oracle_label
     f.restype = ctypes.c_int64
-    f.argtypes = [
-        ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
-        ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
-        ctypes.c_void_p, ctypes.c_void_p,
-    ]
+    f.argtypes = list(_ARGS)
+    if hasattr(lib, "oracle_label_conn"):
+        g = lib.oracle_label_conn
+        g.restype = ctypes.c_int64
+        g.argtypes = list(_ARGS) + [ctypes.c_int32]
     return lib
 
 
@@ -61,15 +68,7 @@ def _load():
     if _lib is None:
         if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
             build()
-        lib = ctypes.CDLL(_LIB)
-        f = lib.oracle_label
-        f.restype = ctypes.c_int64
-        f.argtypes = [
-            ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
-            ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
-            ctypes.c_void_p, ctypes.c_void_p,
-        ]
-        _lib = lib
+        _lib = _bind(ctypes.CDLL(_LIB))
     return _lib
 
 
@@ -91,8 +90,10 @@ class Result:
         return int(self.parent.shape[0])
 
 
-def label(img: np.ndarray, lib=None) -> Result:
-    """Label a 2-D uint8 image (nonzero = foreground); rows may be strided."""
+def label(img: np.ndarray, lib=None, fg8: bool = True) -> Result:
+    """Label a 2-D uint8 image (nonzero = foreground); rows may be strided.
+    fg8=False takes the complementary connectivity pair (4-adjacent
+    foreground, 8-adjacent background)."""
     img = np.asarray(img)
     if img.dtype != np.uint8 or img.ndim != 2:
         raise ValueError("oracle.label expects a 2-D uint8 array")
@@ -108,10 +109,9 @@ def label(img: np.ndarray, lib=None) -> Result:
         feat = np.empty((cap, 7), dtype=np.int64)
         parent = np.empty(cap, dtype=np.int32)
         color = np.empty(cap, dtype=np.uint8)
-        n = lib.oracle_label(
-            img.ctypes.data, w, h, pitch, labels.ctypes.data, cap, feat.ctypes.data,
-            parent.ctypes.data, color.ctypes.data, euler.ctypes.data,
-        )
+        args = (img.ctypes.data, w, h, pitch, labels.ctypes.data, cap, feat.ctypes.data,
+                parent.ctypes.data, color.ctypes.data, euler.ctypes.data)
+        n = lib.oracle_label(*args) if fg8 else lib.oracle_label_conn(*args, 0)
         if n == -3:
             cap = int(labels.max()) + 1 if labels.size else cap * 2
             continue

@@ -146,9 +146,31 @@ static int edge_set_grow(edge_set *s) {
  * Any of feat / parent / color may be NULL to skip that table (the tree is
  * still built and checked).
  */
+int64_t oracle_label_conn(const uint8_t *img, int32_t w, int32_t h, int64_t pitch,
+                          int32_t *labels, int64_t cap, int64_t *feat,
+                          int32_t *parent, uint8_t *color, int64_t *euler,
+                          int32_t fg8);
+
 int64_t oracle_label(const uint8_t *img, int32_t w, int32_t h, int64_t pitch,
                      int32_t *labels, int64_t cap, int64_t *feat,
                      int32_t *parent, uint8_t *color, int64_t *euler) {
+  return oracle_label_conn(img, w, h, pitch, labels, cap, feat, parent, color, euler, 1);
+}
+
+/*
+ * oracle_label_conn: the same with the connectivity pair chosen: fg8 = 1 is
+ * 8-adjacent foreground / 4-adjacent background (the default above); fg8 = 0
+ * the complementary pair, 4-adjacent foreground / 8-adjacent background
+ * (the note on the connectivity pair after the unification algorithm,
+ * Sec. 3.2).  Everything else is unchanged: the frame is background, the
+ * region adjacency graph is built from 4-adjacent pairs (a diagonal contact
+ * between the two colours always comes with a 4-adjacent one), and under
+ * either pair that graph is a tree.
+ */
+int64_t oracle_label_conn(const uint8_t *img, int32_t w, int32_t h, int64_t pitch,
+                          int32_t *labels, int64_t cap, int64_t *feat,
+                          int32_t *parent, uint8_t *color, int64_t *euler,
+                          int32_t fg8) {
   if (!img || !labels || !euler || w <= 0 || h <= 0 || pitch < w) return ORC_EINVAL;
   int64_t n = (int64_t)w * h;
   if (n >= INT32_MAX) return ORC_EINVAL;
@@ -164,18 +186,16 @@ int64_t oracle_label(const uint8_t *img, int32_t w, int32_t h, int64_t pitch,
   for (int32_t y = 0; y < h; y++) {
     for (int32_t x = 0; x < w; x++) {
       int64_t me = NODE(y, x);
-      if (FG(y, x)) {
-        if (x > 0 && FG(y, x - 1)) unite(par, me, NODE(y, x - 1));
-        if (y > 0) {
-          if (x > 0 && FG(y - 1, x - 1)) unite(par, me, NODE(y - 1, x - 1));
-          if (FG(y - 1, x)) unite(par, me, NODE(y - 1, x));
-          if (x + 1 < w && FG(y - 1, x + 1)) unite(par, me, NODE(y - 1, x + 1));
-        }
-      } else {
-        if (x > 0 && !FG(y, x - 1)) unite(par, me, NODE(y, x - 1));
-        if (y > 0 && !FG(y - 1, x)) unite(par, me, NODE(y - 1, x));
-        if (x == 0 || y == 0 || x == w - 1 || y == h - 1) unite(par, me, 0);
+      int v = FG(y, x);
+      int diag = fg8 ? v : !v; /* this colour is 8-adjacent */
+      /* W and N for both colours; NW and NE for the 8-adjacent colour */
+      if (x > 0 && FG(y, x - 1) == v) unite(par, me, NODE(y, x - 1));
+      if (y > 0) {
+        if (FG(y - 1, x) == v) unite(par, me, NODE(y - 1, x));
+        if (diag && x > 0 && FG(y - 1, x - 1) == v) unite(par, me, NODE(y - 1, x - 1));
+        if (diag && x + 1 < w && FG(y - 1, x + 1) == v) unite(par, me, NODE(y - 1, x + 1));
       }
+      if (!v && (x == 0 || y == 0 || x == w - 1 || y == h - 1)) unite(par, me, 0);
     }
   }
 

@@ -32,8 +32,9 @@ N4 = ((-1, 0), (1, 0), (0, -1), (0, 1))
 N8 = N4 + ((-1, -1), (-1, 1), (1, -1), (1, 1))
 
 
-def flood_label(img: np.ndarray) -> np.ndarray:
-    """Canonical labels by flood fill (exterior = 0, others by first raster pixel)."""
+def flood_label(img: np.ndarray, fg8: bool = True) -> np.ndarray:
+    """Canonical labels by flood fill (exterior = 0, others by first raster pixel).
+    fg8=False: 4-adjacent foreground, 8-adjacent background."""
     fg = np.asarray(img) != 0
     h, w = fg.shape
     lab = np.full((h, w), -1, dtype=np.int64)
@@ -44,7 +45,7 @@ def flood_label(img: np.ndarray) -> np.ndarray:
             if lab[y, x] < 0 and fg[y, x] == colour:
                 lab[y, x] = k
                 q.append((y, x))
-        nb = N8 if colour else N4
+        nb = N8 if colour == fg8 else N4
         while q:
             y, x = q.popleft()
             for dy, dx in nb:
@@ -86,15 +87,16 @@ def adjacent_components(lab: np.ndarray) -> dict:
     return adj
 
 
-def surrounds(lab: np.ndarray, fg: np.ndarray, c: int, d: int) -> bool:
+def surrounds(lab: np.ndarray, fg: np.ndarray, c: int, d: int, fg8: bool = True) -> bool:
     """True when every path from component c to outside the image meets d.
-    Paths use c's own adjacency (8 for foreground, 4 for background)."""
+    Paths use c's own adjacency (8 for foreground, 4 for background, or the
+    complementary pair when fg8 is False)."""
     if d == 0:
         return True  # the exterior frame lies on every path leaving the image
     h, w = lab.shape
     ys, xs = np.nonzero(lab == c)
     colour = bool(fg[ys[0], xs[0]])
-    nb = N8 if colour else N4
+    nb = N8 if colour == fg8 else N4
     seen = np.zeros((h, w), dtype=bool)
     q = deque()
     for y, x in zip(ys, xs):
@@ -112,7 +114,7 @@ def surrounds(lab: np.ndarray, fg: np.ndarray, c: int, d: int) -> bool:
     return True
 
 
-def flood_tree(img: np.ndarray, lab: np.ndarray) -> np.ndarray:
+def flood_tree(img: np.ndarray, lab: np.ndarray, fg8: bool = True) -> np.ndarray:
     """parent[c] = the unique adjacent component surrounding c; parent[0] = -1.
     Raises AssertionError when uniqueness fails."""
     fg = np.asarray(img) != 0
@@ -121,7 +123,7 @@ def flood_tree(img: np.ndarray, lab: np.ndarray) -> np.ndarray:
     parent = np.full(n, -2, dtype=np.int64)
     parent[0] = -1
     for c in range(1, n):
-        cands = [d for d in sorted(adj[c]) if surrounds(lab, fg, c, d)]
+        cands = [d for d in sorted(adj[c]) if surrounds(lab, fg, c, d, fg8)]
         assert len(cands) == 1, (c, cands)
         parent[c] = cands[0]
     return parent
@@ -183,13 +185,15 @@ def _merge_features(f, g):
             f[4] + g[4], f[5] + g[5], f[6] + g[6]]
 
 
-def lsl_bw(img: np.ndarray, fix_bottom: bool = True, fill_holes: bool = False):
+def lsl_bw(img: np.ndarray, fix_bottom: bool = True, fill_holes: bool = False, fg8: bool = True):
     """Returns (final_labels_per_pixel, T, I, events, F, rows).
 
     fill_holes: the closure's optional step (Algorithm 3): a root whose
     surrounding's final label is not the exterior is merged into that
     surrounding before the closure continues, so nested levels cascade into
     the top-level foreground.
+    fg8=False: the complementary connectivity pair (the run widening applies
+    to background runs instead of foreground ones).
 
     events: list of ("new", row, label, colour, surrounding) and
     ("equiv", row, kept, merged) in scan order; labels are provisional.
@@ -218,7 +222,7 @@ def lsl_bw(img: np.ndarray, fix_bottom: bool = True, fill_holes: bool = False):
                 era[k] = 0  # empty leading background run
                 continue
             colour = k % 2 == 1
-            widen = 1 if colour else 0  # foreground 8-adjacent, background 4-adjacent
+            widen = 1 if colour == fg8 else 0  # the 8-adjacent colour's runs are widened
             lo, hi = max(j0 - widen, 0), min(j1 + widen, w)
             above = []
             if prev is None:

@@ -13,11 +13,10 @@ from golden import fig2
 SRC = os.path.join(os.path.dirname(oracle.__file__), "ccl_oracle.c")
 
 MUTANTS = {
-    "drop_NE_neighbour": ("if (x + 1 < w && FG(y - 1, x + 1)) unite(par, me, NODE(y - 1, x + 1));", ""),
-    "drop_NW_neighbour": ("if (x > 0 && FG(y - 1, x - 1)) unite(par, me, NODE(y - 1, x - 1));", ""),
-    "bg_8_connected": ("if (y > 0 && !FG(y - 1, x)) unite(par, me, NODE(y - 1, x));",
-                       "if (y > 0 && !FG(y - 1, x)) unite(par, me, NODE(y - 1, x));\n"
-                       "        if (y > 0 && x > 0 && !FG(y - 1, x - 1)) unite(par, me, NODE(y - 1, x - 1));"),
+    "drop_NE_neighbour": ("if (diag && x + 1 < w && FG(y - 1, x + 1) == v) unite(par, me, NODE(y - 1, x + 1));", ""),
+    "drop_NW_neighbour": ("if (diag && x > 0 && FG(y - 1, x - 1) == v) unite(par, me, NODE(y - 1, x - 1));", ""),
+    "bg_8_connected": ("int diag = fg8 ? v : !v;", "int diag = 1;"),
+    "fg_4_connected": ("int diag = fg8 ? v : !v;", "int diag = 0;"),
     "no_bottom_frame": ("x == w - 1 || y == h - 1", "x == w - 1"),
     "sx_sums_row": ("f[5] += x;", "f[5] += y;"),
     "bbox_xmax_off_by_one": ("if (x > f[1]) f[1] = x;", "if (x > f[1]) f[1] = x + 1;"),
