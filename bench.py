@@ -339,8 +339,9 @@ def run_serve(n_requests: int, rate_hz: float = 2000.0, warmup_s: float = 1.0, p
 
 def run_fill_and_features_only(work, reps: int = 3):
     """Widened rows of the path, on the same images: hole filling after a
-    labeling (ccl_fill_holes, filled label image and tables), and the
-    features-only mode (ccl_label with no label image).  Per image: label
+    labeling (ccl_fill_holes, filled label image and tables), the
+    features-only mode (ccl_label with no label image) and the complementary
+    connectivity pair (ccl_label_conn, 4-adjacent foreground).  Per image: label
     once, then `reps` timed calls (events on the stream the kernels run on)."""
     import torch
     import paper_2006_09299_amd as ccl
@@ -352,6 +353,7 @@ def run_fill_and_features_only(work, reps: int = 3):
     h, w = work[0][1].shape
     buf = ccl.Buffers(w, h, w * h // 4 + 1024, dev)
     fo = ccl.Buffers(w, h, w * h // 4 + 1024, dev, labels=False)
+    c4 = ccl.Buffers(w, h, w * h // 4 + 1024, dev)
     olab = torch.empty((h, w), dtype=torch.int32, device=dev)
     ofeat = torch.empty((buf.cap, 5), dtype=torch.int64, device=dev)
     opar = torch.empty(buf.cap, dtype=torch.int32, device=dev)
@@ -361,15 +363,18 @@ def run_fill_and_features_only(work, reps: int = 3):
                               oc.data_ptr())
     wsb = int(lib.ccl_fill_workspace_bytes(buf.cap))
     ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
-    fill_ms, fo_ms, label_ms, px, fill_bytes = 0.0, 0.0, 0.0, 0, 0
+    fill_ms, fo_ms, c4_ms, label_ms, px, fill_bytes = 0.0, 0.0, 0.0, 0.0, 0, 0
     for _, img in work:
         t = torch.from_numpy(img).to(dev)
         ccl.launch(t, buf)  # warm
         ccl.launch(t, fo)
+        ccl.launch(t, c4, fg_adjacency=4)
         torch.cuda.synchronize()
         n_lab = int(buf.counts[0].item())
+        if int(c4.counts[0].item()) > c4.cap:
+            raise RuntimeError("table capacity too small for the complementary pair")
         for _ in range(reps + 1):  # the first of each is a warm-up
-            e = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(8)]
             e[0].record(stream)
             ccl.launch(t, buf)
             e[1].record(stream)
@@ -381,11 +386,15 @@ def run_fill_and_features_only(work, reps: int = 3):
             e[4].record(stream)
             ccl.launch(t, fo)
             e[5].record(stream)
+            e[6].record(stream)
+            ccl.launch(t, c4, fg_adjacency=4)
+            e[7].record(stream)
             torch.cuda.synchronize()
             if _ > 0:
                 label_ms += e[0].elapsed_time(e[1])
                 fill_ms += e[2].elapsed_time(e[3])
                 fo_ms += e[4].elapsed_time(e[5])
+                c4_ms += e[6].elapsed_time(e[7])
         n_fill = int(oc[0].item())
         px += w * h * reps
         # read the label image and the labeling's tables, write the filled ones
@@ -396,7 +405,8 @@ def run_fill_and_features_only(work, reps: int = 3):
             "fill_holes": {"Gpixel_s": gps(fill_ms), "ms_per_image": round(fill_ms / (px / (w * h)), 4),
                            "label_plus_fill_Gpixel_s": gps(label_ms + fill_ms),
                            "alg_GBs": round(fill_gbs, 1), "hbm_frac": round(fill_gbs / HBM_PEAK_GBS, 4)},
-            "features_only": {"Gpixel_s": gps(fo_ms), "ms_per_image": round(fo_ms / (px / (w * h)), 4)}}
+            "features_only": {"Gpixel_s": gps(fo_ms), "ms_per_image": round(fo_ms / (px / (w * h)), 4)},
+            "fg4_bg8": {"Gpixel_s": gps(c4_ms), "ms_per_image": round(c4_ms / (px / (w * h)), 4)}}
 
 
 def cpu_baseline(work, budget_s: float = 15.0):
@@ -452,7 +462,7 @@ def main():
 
     if args.fill_only:
         fx = run_fill_and_features_only(make_workload("sweep8192"), reps=1)
-        print(json.dumps({"fill_and_features_only_sweep8192": fx}), flush=True)
+        print(json.dumps({"widened_sweep8192": fx}), flush=True)
         return
     say(f"bench: workload {args.workload}, steps {args.steps}, warmup {args.warmup}")
     work = make_workload(args.workload)
@@ -492,10 +502,10 @@ def main():
             "roofline": roofline(r2, "structured16384"),
             "kernel_avg_ms": {k: round(v, 5) for k, v in r2["kernel_avg_ms"].items()}}}
     if args.workload == "sweep8192" and not args.no_also:
-        say("bench: hole filling and features-only mode on the same images")
+        say("bench: hole filling, features-only mode and the 4/8 connectivity pair on the same images")
         fx = run_fill_and_features_only(work)
         say(f"  {json.dumps(fx)}")
-        out.setdefault("also", {})["fill_and_features_only_sweep8192"] = fx
+        out.setdefault("also", {})["widened_sweep8192"] = fx
     if args.workload == "sweep8192" and not args.no_also:
         say("bench: secondary workload batch4096")
         out.setdefault("also", {})["batch4096"] = run_batch(4096, max(3, args.steps), 1)

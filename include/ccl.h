@@ -87,6 +87,15 @@ size_t ccl_workspace_bytes(int32_t w, int32_t h);
 int ccl_label(const uint8_t *img, int32_t w, int32_t h, int64_t pitch, const ccl_outputs_t *out, void *ws,
               size_t ws_bytes, void *stream);
 
+/* ccl_label with the connectivity pair chosen (the note after the
+ * unification algorithm, Sec. 3.2): fg_adjacency = 8 is the default pair
+ * (8-adjacent foreground, 4-adjacent background); 4 the complementary one
+ * (4-adjacent foreground, 8-adjacent background: components, tree and
+ * Euler number E = #foreground components - #holes under that pair).  Same
+ * workspace as ccl_label; CCL_EINVAL for any other fg_adjacency. */
+int ccl_label_conn(const uint8_t *img, int32_t w, int32_t h, int64_t pitch, const ccl_outputs_t *out, void *ws,
+                   size_t ws_bytes, void *stream, int32_t fg_adjacency);
+
 /* Number of HIP events ccl_label_traced records: one before each of the
  * path's ten kernels, in launch order, and one after the last. */
 #define CCL_TRACE_EVENTS 11

@@ -85,30 +85,41 @@ def _check_image(img: torch.Tensor):
     return int(w), int(h), int(pitch)
 
 
-def launch(img: torch.Tensor, buf: Buffers, stream: Optional[int] = None) -> None:
-    """Enqueue one labeling into preallocated buffers (no synchronisation)."""
+def launch(img: torch.Tensor, buf: Buffers, stream: Optional[int] = None, fg_adjacency: int = 8) -> None:
+    """Enqueue one labeling into preallocated buffers (no synchronisation).
+    fg_adjacency=4 takes the complementary connectivity pair (default variant
+    only)."""
     w, h, pitch = _check_image(img)
     if (w, h) != (buf.w, buf.h):
         raise ValueError("buffers were made for another shape")
     if stream is None:
         stream = torch.cuda.current_stream(img.device).cuda_stream
-    rc = _capi.lib().ccl_label_v(img.data_ptr(), w, h, pitch, ctypes.byref(buf.out), buf.ws.data_ptr(),
-                                 buf.ws_bytes, ctypes.c_void_p(stream), buf.variant)
+    if fg_adjacency == 8:
+        rc = _capi.lib().ccl_label_v(img.data_ptr(), w, h, pitch, ctypes.byref(buf.out), buf.ws.data_ptr(),
+                                     buf.ws_bytes, ctypes.c_void_p(stream), buf.variant)
+    else:
+        if buf.variant != 0:
+            raise ValueError("the complementary connectivity pair is compiled for the default variant only")
+        rc = _capi.lib().ccl_label_conn(img.data_ptr(), w, h, pitch, ctypes.byref(buf.out), buf.ws.data_ptr(),
+                                        buf.ws_bytes, ctypes.c_void_p(stream), int(fg_adjacency))
     _capi.check(rc, "ccl_label")
 
 
-def label(img: torch.Tensor, cap: Optional[int] = None, labels: bool = True, variant: int = 0) -> Result:
+def label(img: torch.Tensor, cap: Optional[int] = None, labels: bool = True, variant: int = 0,
+          fg_adjacency: int = 8) -> Result:
     """Label one image; synchronises to read the number of labels.
 
     cap: table capacity; by default a quarter of the pixels, grown and rerun
-    when the image has more components (w*h + 1 always suffices)."""
+    when the image has more components (w*h + 1 always suffices).
+    fg_adjacency: 8 (8-adjacent foreground, 4-adjacent background) or 4 (the
+    complementary pair)."""
     w, h, pitch = _check_image(img)
     full = w * h + 1
     if cap is None:
         cap = min(full, max(1024, full // 4))
     while True:
         buf = Buffers(w, h, cap, img.device, labels=labels, variant=variant)
-        launch(img, buf)
+        launch(img, buf, fg_adjacency=fg_adjacency)
         counts = buf.counts.cpu()
         n, euler = int(counts[0]), int(counts[1])
         if n <= cap:

@@ -70,7 +70,7 @@ EXPORTS = (
     "ccl_variant_info", "ccl_workspace_bytes_v", "ccl_label_v", "ccl_batch_sizes", "ccl_batch_prepare",
     "ccl_label_batch", "ccl_strerror", "ccl_tile_shape", "ccl_server_create", "ccl_server_footprint",
     "ccl_server_submit", "ccl_server_poll", "ccl_server_release", "ccl_server_stats", "ccl_server_destroy",
-    "ccl_fill_workspace_bytes", "ccl_fill_holes",
+    "ccl_fill_workspace_bytes", "ccl_fill_holes", "ccl_label_conn",
 )
 TRACE_EVENTS = 11
 
@@ -145,6 +145,8 @@ def lib():
         L.ccl_fill_holes.restype = ctypes.c_int
         L.ccl_fill_holes.argtypes = [ctypes.POINTER(ccl_outputs_t), i32, i32, ctypes.POINTER(ccl_outputs_t), vp, vp,
                                      ctypes.c_size_t, vp]
+        L.ccl_label_conn.restype = ctypes.c_int
+        L.ccl_label_conn.argtypes = [vp, i32, i32, i64, ctypes.POINTER(ccl_outputs_t), vp, ctypes.c_size_t, vp, i32]
         L.ccl_tile_shape.restype = None
         L.ccl_tile_shape.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
         _lib = L

@@ -17,11 +17,15 @@ namespace {
 static_assert(sizeof(ccl::Feature) == sizeof(ccl_feature_t), "feature record layout");
 static_assert(sizeof(ccl::ImgDesc) <= 256, "the serving footprint counts one 256-byte block per descriptor");
 
-template <int TH, int TW, bool HASH, int NT = 256>
+template <int TH, int TW, bool HASH, int NT = 256, bool FG8 = true>
 struct V {
-  using T = ccl::Tile<TH, TW, NT>;
+  using T = ccl::Tile<TH, TW, NT, FG8>;
   static constexpr bool hash = HASH;
 };
+
+// the complementary connectivity pair (4-adjacent foreground, 8-adjacent
+// background) in the default variant's shape
+using VC4 = V<64, 128, true, 256, false>;
 
 // variant index -> (tile rows, tile columns, reduction, workgroup size)
 constexpr int NVARIANTS = 8;
@@ -104,9 +108,10 @@ int place_batch(const ccl_image_t* imgs, int32_t n, ccl::ImgDesc* ds, Totals& t)
 }
 
 int label_one(const uint8_t* img, int32_t w, int32_t h, int64_t pitch, const ccl_outputs_t* out, void* ws,
-              size_t ws_bytes, void* stream, void* const* events, int32_t variant) {
+              size_t ws_bytes, void* stream, void* const* events, int32_t variant, bool fg8 = true) {
   if (!image_args_ok(img, w, h, pitch, out) || !ws) return CCL_EINVAL;
-  return with_variant(variant, [&](auto vt) -> int {
+  auto pick = [&](auto&& f) -> int { return fg8 ? with_variant(variant, f) : f(VC4{}); };
+  return pick([&](auto vt) -> int {
     using Vt = decltype(vt);
     using T = typename Vt::T;
     ccl::ImgDesc d = to_desc(img, w, h, pitch, out);
@@ -239,6 +244,12 @@ int ccl_label(const uint8_t* img, int32_t w, int32_t h, int64_t pitch, const ccl
 int ccl_label_v(const uint8_t* img, int32_t w, int32_t h, int64_t pitch, const ccl_outputs_t* out, void* ws,
                 size_t ws_bytes, void* stream, int32_t variant) {
   return label_one(img, w, h, pitch, out, ws, ws_bytes, stream, nullptr, variant);
+}
+
+int ccl_label_conn(const uint8_t* img, int32_t w, int32_t h, int64_t pitch, const ccl_outputs_t* out, void* ws,
+                   size_t ws_bytes, void* stream, int32_t fg_adjacency) {
+  if (fg_adjacency != 8 && fg_adjacency != 4) return CCL_EINVAL;
+  return label_one(img, w, h, pitch, out, ws, ws_bytes, stream, nullptr, 0, fg_adjacency == 8);
 }
 
 int ccl_label_traced(const uint8_t* img, int32_t w, int32_t h, int64_t pitch, const ccl_outputs_t* out, void* ws,

@@ -141,7 +141,7 @@ constexpr int SUP = 4;                  // tiles per side of a super-tile (seams
 constexpr int SCAN_T = 256;             // threads of the scan kernels
 constexpr int SCAN_B = SCAN_T * 4;      // entries per scan block
 
-template <int TH_, int TW_, int NT_ = 256>
+template <int TH_, int TW_, int NT_ = 256, bool FG8_ = true>
 struct Tile {
   static constexpr int TH = TH_;
   static constexpr int TW = TW_;
@@ -152,6 +152,9 @@ struct Tile {
   static constexpr int NCH = TH * CPR;     // chunks per tile
   static constexpr int BCAP = 2 * (TH + TW);  // >= border pixels >= border nodes
   static constexpr int NT = NT_;           // threads per tile workgroup
+  // connectivity pair: 8-adjacent foreground / 4-adjacent background, or
+  // the complementary pair (the unification's widening moves to background)
+  static constexpr bool FG8 = FG8_;
   static constexpr int CAPI = N >= 8192 ? 512 : 256;  // interior accumulators per pass
   static_assert(TW % 64 == 0 && TW <= 256, "tile width (a row rank fits 8 bits)");
   static_assert(TH >= 1 && TH <= 64, "tile height (a column of the tile fits one wave)");
@@ -310,20 +313,46 @@ __device__ inline void gunion(int32_t* gp, int a, int b) {
 //   da:   foreground diagonal to the upper right, unite with run(upper, x+1)
 //         (the lower run ends at x, the upper run starts at x+1);
 //   db:   foreground diagonal to the upper left, unite with run(upper, x-1).
+// Vn: valid bits of the word after.  With the complementary connectivity
+// pair (FG8 false) the diagonals are those of the background: the same
+// formulas on the background bits of the valid pixels.
 struct PairMasks { u64 vert, da, db; };
-__device__ inline PairMasks pair_masks(u64 m0, u64 m1, u64 m0p, u64 m1p, u64 m0n, u64 m1n, u64 V, bool pfull) {
+template <bool FG8>
+__device__ inline PairMasks pair_masks(u64 m0, u64 m1, u64 m0p, u64 m1p, u64 m0n, u64 m1n, u64 V, bool pfull,
+                                       u64 Vn) {
   PairMasks r;
   u64 F = m0 & m1, Fp = m0p & m1p;
   u64 Fv = F & ~((F << 1) | (Fp >> 63));
   u64 B = ~m0 & ~m1 & V;
   u64 Bp = pfull ? (~m0p & ~m1p) : 0ull;
   u64 Bv = B & ~((B << 1) | (Bp >> 63));
+  r.vert = Fv | Bv;
+  if (!FG8) {  // diagonal colour: background
+    m0 = ~m0 & V;
+    m1 = ~m1 & V;
+    m0n = ~m0n & Vn;
+    m1n = ~m1n & Vn;
+    m0p = pfull ? ~m0p : 0ull;
+    m1p = pfull ? ~m1p : 0ull;
+  }
   u64 R1 = (m1 >> 1) | (m1n << 63), R0 = (m0 >> 1) | (m0n << 63);
   u64 L1 = (m1 << 1) | (m1p >> 63), L0 = (m0 << 1) | (m0p >> 63);
-  r.vert = Fv | Bv;
   r.da = m0 & ~m1 & R1 & ~R0 & V;
   r.db = m0 & ~m1 & L1 & ~L0 & V;
   return r;
+}
+
+// Diagonal contacts across a vertical seam between rows y-1 and y: a, b the
+// pixels left / right of the seam in row y, c, dd in row y-1 (1 =
+// foreground).  Only the diagonal colour's contacts count, and only where
+// the crossing diagonal has the other colour (else a 4-path joins them).
+template <bool FG8>
+__device__ inline bool diag_right_up(int a, int b, int c, int dd) {  // (right, y) with (left, y-1)
+  return FG8 ? (b && c && !a && !dd) : (!b && !c && a && dd);
+}
+template <bool FG8>
+__device__ inline bool diag_left_up(int a, int b, int c, int dd) {  // (left, y) with (right, y-1)
+  return FG8 ? (a && dd && !b && !c) : (!a && !dd && b && c);
 }
 
 // packed per-component accumulators: S | Sx << 16 | Sy << 40 (tile-local
@@ -519,7 +548,7 @@ __device__ void tile_unite(TileSmem<T>& s, u32* stage_all, int stage_words, int 
       u64 m0 = B0[j], m1 = B1[j];
       u64 m0p = j ? B0[j - 1] : 0ull, m1p = j ? B1[j - 1] : 0ull;
       u64 m0n = j + 1 < T::WPR ? B0[j + 1] : 0ull, m1n = j + 1 < T::WPR ? B1[j + 1] : 0ull;
-      PairMasks pm = pair_masks(m0, m1, m0p, m1p, m0n, m1n, valid_mask(j, tw), j > 0);
+      PairMasks pm = pair_masks<T::FG8>(m0, m1, m0p, m1p, m0n, m1n, valid_mask(j, tw), j > 0, valid_mask(j + 1, tw));
       pts = ((pm.vert >> sh) & 0xFFFFull) | (((pm.da >> sh) & 0xFFFFull) << 16) |
             (((pm.db >> sh) & 0xFFFFull) << 32);
       xb = j * 64 + sh;
@@ -1047,7 +1076,8 @@ __global__ void __launch_bounds__(256) k_seam_local(Src src, Work wk) {
       u64 m0 = seam_bits<T>(wk, d, e, jw, false), m1 = seam_bits<T>(wk, d, e - 1, jw, true);
       u64 m0p = seam_bits<T>(wk, d, e, jw - 1, false), m1p = seam_bits<T>(wk, d, e - 1, jw - 1, true);
       u64 m0n = seam_bits<T>(wk, d, e, jw + 1, false), m1n = seam_bits<T>(wk, d, e - 1, jw + 1, true);
-      PairMasks pm = pair_masks(m0, m1, m0p, m1p, m0n, m1n, valid_mask(jw, d.w), jw > 0);
+      PairMasks pm = pair_masks<T::FG8>(m0, m1, m0p, m1p, m0n, m1n, valid_mask(jw, d.w), jw > 0,
+                                         valid_mask(jw + 1, d.w));
       u64 pts = ((pm.vert >> sh) & 0xFFFFull) | (((pm.da >> sh) & 0xFFFFull) << 16) |
                 (((pm.db >> sh) & 0xFFFFull) << 32);
       while (pts) {
@@ -1077,8 +1107,8 @@ __global__ void __launch_bounds__(256) k_seam_local(Src src, Work wk) {
       auto right = [&](int yy) { return lnode_of<T>(wk, d, tx0, ty0, e, ty, wk.bidx_left[gR * T::TH + yy % T::TH]); };
       if (a == b && !(ly > 0 && c == a && dd == b)) lunion(lp, (u32)left(y), (u32)right(y));
       if (ly > 0) {
-        if (b && c && !a && !dd) lunion(lp, (u32)right(y), (u32)left(y - 1));
-        if (a && dd && !b && !c) lunion(lp, (u32)left(y), (u32)right(y - 1));
+        if (diag_right_up<T::FG8>(a, b, c, dd)) lunion(lp, (u32)right(y), (u32)left(y - 1));
+        if (diag_left_up<T::FG8>(a, b, c, dd)) lunion(lp, (u32)left(y), (u32)right(y - 1));
       }
     }
   }
@@ -1131,7 +1161,8 @@ __global__ void __launch_bounds__(256) k_border_merge(Src src, Work wk, int64_t 
     u64 m0 = seam_bits<T>(wk, d, e, jw, false), m1 = seam_bits<T>(wk, d, e - 1, jw, true);
     u64 m0p = seam_bits<T>(wk, d, e, jw - 1, false), m1p = seam_bits<T>(wk, d, e - 1, jw - 1, true);
     u64 m0n = seam_bits<T>(wk, d, e, jw + 1, false), m1n = seam_bits<T>(wk, d, e - 1, jw + 1, true);
-    PairMasks pm = pair_masks(m0, m1, m0p, m1p, m0n, m1n, valid_mask(jw, d.w), jw > 0);
+    PairMasks pm = pair_masks<T::FG8>(m0, m1, m0p, m1p, m0n, m1n, valid_mask(jw, d.w), jw > 0,
+                                         valid_mask(jw + 1, d.w));
     int xb = jw * 64;
     u64 m = pm.vert;
     if (inner) {  // only the diagonals that cross a super-tile column edge
@@ -1171,8 +1202,10 @@ __global__ void __launch_bounds__(256) k_border_merge(Src src, Work wk, int64_t 
     if (a == b && !(ly > 0 && c == a && dd == b))
       gunion(wk.gpar, col_node<T>(wk, d, e - 1, y, true), col_node<T>(wk, d, e, y, false));
     if (ly > 0) {
-      if (b && c && !a && !dd) gunion(wk.gpar, col_node<T>(wk, d, e, y, false), col_node<T>(wk, d, e - 1, y - 1, true));
-      if (a && dd && !b && !c) gunion(wk.gpar, col_node<T>(wk, d, e - 1, y, true), col_node<T>(wk, d, e, y - 1, false));
+      if (diag_right_up<T::FG8>(a, b, c, dd))
+        gunion(wk.gpar, col_node<T>(wk, d, e, y, false), col_node<T>(wk, d, e - 1, y - 1, true));
+      if (diag_left_up<T::FG8>(a, b, c, dd))
+        gunion(wk.gpar, col_node<T>(wk, d, e - 1, y, true), col_node<T>(wk, d, e, y - 1, false));
     }
     return;
   }
@@ -2003,7 +2036,7 @@ inline void enqueue(Launcher& L, const Src& src, const Work& wk, int64_t tiles, 
   // whatever the other kernels use: it is bound by memory latency and its
   // LDS (not wave slots) limits the workgroups per CU, so wider workgroups
   // keep more waves in flight (measured: faster than 256 and than 1024).
-  using TE = Tile<T::TH, T::TW, (T::N >= 8192 && T::NT < 512 ? 512 : T::NT)>;
+  using TE = Tile<T::TH, T::TW, (T::N >= 8192 && T::NT < 512 ? 512 : T::NT), T::FG8>;
   L.launch(k_tile_emit<TE, Src>, tiles, TE::NT, src, wk);
 }
 

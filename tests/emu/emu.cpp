@@ -311,6 +311,8 @@ int main(int argc, char** argv) {
     case 5: run_images<ccl::Tile<1, 64>>(ims, batch); break;
     case 6: run_images<ccl::Tile<16, 128, 512>>(ims, batch); break;
     case 7: run_images<ccl::Tile<64, 128>>(ims, batch); break;  // relabeling with 512 threads
+    case 8: run_images<ccl::Tile<32, 128, 256, false>>(ims, batch); break;  // 4-adjacent foreground
+    case 9: run_images<ccl::Tile<4, 64, 256, false>>(ims, batch); break;
     default: fprintf(stderr, "bad tile config\n"); return 2;
   }
   FILE* fo = fopen(argv[4], "wb");

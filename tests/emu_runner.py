@@ -27,7 +27,8 @@ EXE = os.path.join(BUILD, "ccl_emu")
 CXX = "/opt/rocm/llvm/bin/clang++" if os.path.exists("/opt/rocm/llvm/bin/clang++") else "clang++"
 
 # tile configurations compiled into the emulator: (rows, columns)
-TILES = {0: (32, 128), 1: (4, 64), 2: (3, 64), 3: (5, 192), 4: (64, 64), 5: (1, 64), 6: (16, 128), 7: (64, 128)}  # 6: 512 threads; 7: 256, relabeling 512
+TILES = {0: (32, 128), 1: (4, 64), 2: (3, 64), 3: (5, 192), 4: (64, 64), 5: (1, 64), 6: (16, 128), 7: (64, 128), 8: (32, 128), 9: (4, 64)}
+# 6: 512 threads; 7: 256, relabeling 512; 8, 9: 4-adjacent foreground, 8-adjacent background
 
 
 def build(force: bool = False) -> str:

@@ -122,3 +122,13 @@ def test_fill_holes_rejects_bad_arguments_on_host():
     assert call(good_in, 8, 8, _capi.ccl_outputs_t(fake, fake, fake, fake, 0, fake)) == E
     assert call(good_in, 8, 8, good_out, ws=None) == E
     assert call(good_in, 8, 8, good_out, n=wsb - 1) == _capi.CCL_ENOSPC
+
+
+def test_label_conn_rejects_other_adjacencies_on_host():
+    L = _capi.lib()
+    fake = 0x1000  # never dereferenced: every case fails validation first
+    out = _capi.ccl_outputs_t(fake, fake, fake, fake, 10, fake)
+    wsb = _capi.workspace_bytes(64, 64)
+    for adj in (0, 1, 6, 16, -8):
+        assert L.ccl_label_conn(fake, 64, 64, 64, ctypes.byref(out), fake, wsb, None, adj) == _capi.CCL_EINVAL
+    assert L.ccl_label_conn(None, 64, 64, 64, ctypes.byref(out), fake, wsb, None, 4) == _capi.CCL_EINVAL

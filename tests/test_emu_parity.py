@@ -14,8 +14,8 @@ import synth
 from golden import fig2
 
 
-def _assert_same(img, r):
-    o = oracle.label(img)
+def _assert_same(img, r, fg8=True):
+    o = oracle.label(img, fg8=fg8)
     assert r.n_labels == o.n_labels and r.euler == o.euler
     assert np.array_equal(r.labels, o.labels)
     assert np.array_equal(r.parent, o.parent)
@@ -74,3 +74,15 @@ def test_emulated_kernels_other_thread_orders(sched):
     imgs = _cases(22, 6, 30, 200)
     for img, r in zip(imgs, emu_runner.run(imgs, tile_cfg=1, batch=True, sched=sched)):
         _assert_same(img, r)
+
+
+@pytest.mark.parametrize("cfg", [8, 9])
+def test_emulated_kernels_complementary_connectivity(cfg):
+    """4-adjacent foreground / 8-adjacent background (background diagonals
+    inside tiles, across tile seams and corners)"""
+    imgs = _cases(200 + cfg, 8, 40, 300)
+    for img, r in zip(imgs, emu_runner.run(imgs, tile_cfg=cfg)):
+        _assert_same(img, r, fg8=False)
+    imgs = _cases(300 + cfg, 6, 30, 200)
+    for img, r in zip(imgs, emu_runner.run(imgs, tile_cfg=cfg, batch=True, pitch_pad=3)):
+        _assert_same(img, r, fg8=False)
