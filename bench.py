@@ -337,7 +337,7 @@ def run_serve(n_requests: int, rate_hz: float = 2000.0, warmup_s: float = 1.0, p
             "micro_batches": st.launches, "relaunched": st.relaunched}
 
 
-def run_fill_and_features_only(work, reps: int = 3):
+def run_widened(work, reps: int = 3):
     """Widened rows of the path, on the same images: hole filling after a
     labeling (ccl_fill_holes, filled label image and tables), the
     features-only mode (ccl_label with no label image) and the complementary
@@ -461,7 +461,7 @@ def main():
         sys.exit(2)
 
     if args.fill_only:
-        fx = run_fill_and_features_only(make_workload("sweep8192"), reps=1)
+        fx = run_widened(make_workload("sweep8192"), reps=1)
         print(json.dumps({"widened_sweep8192": fx}), flush=True)
         return
     say(f"bench: workload {args.workload}, steps {args.steps}, warmup {args.warmup}")
@@ -503,7 +503,7 @@ def main():
             "kernel_avg_ms": {k: round(v, 5) for k, v in r2["kernel_avg_ms"].items()}}}
     if args.workload == "sweep8192" and not args.no_also:
         say("bench: hole filling, features-only mode and the 4/8 connectivity pair on the same images")
-        fx = run_fill_and_features_only(work)
+        fx = run_widened(work)
         say(f"  {json.dumps(fx)}")
         out.setdefault("also", {})["widened_sweep8192"] = fx
     if args.workload == "sweep8192" and not args.no_also:
