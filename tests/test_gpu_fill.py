@@ -125,3 +125,61 @@ def test_small_output_capacity_keeps_true_counts():
 @pytest.mark.parametrize("p,g,seed", [(0.5, 1, 102), (0.3, 4, 111)])
 def test_full_size_8192(p, g, seed):
     _check(synth.bernoulli_blocks(8192, 8192, p, g, seed))
+
+
+def test_label_then_fill_captured_in_one_graph():
+    """ccl_label followed by ccl_fill_holes on the same stream needs no host
+    synchronisation (the fill reads the label count on the device), so both
+    go into one HIP graph; replays with eager work between them, then new
+    pixels in the same input buffer."""
+    import ctypes
+
+    import paper_2006_09299_amd as ccl
+    from paper_2006_09299_amd import _capi
+    dev = _dev()
+    img = synth.bernoulli_blocks(600, 900, 0.5, 2, 17)
+    h, w = img.shape
+    t = torch.from_numpy(img).to(dev)
+    cap = w * h // 2 + 16
+    buf = ccl.Buffers(w, h, cap, dev)
+    olab = torch.empty((h, w), dtype=torch.int32, device=dev)
+    ofeat = torch.empty((cap, 5), dtype=torch.int64, device=dev)
+    opar = torch.empty(cap, dtype=torch.int32, device=dev)
+    ocol = torch.empty(cap, dtype=torch.uint8, device=dev)
+    oc = torch.zeros(2, dtype=torch.int64, device=dev)
+    out = _capi.ccl_outputs_t(olab.data_ptr(), ofeat.data_ptr(), opar.data_ptr(), ocol.data_ptr(), cap, oc.data_ptr())
+    wsb = int(_capi.lib().ccl_fill_workspace_bytes(cap))
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+
+    def seq():
+        ccl.launch(t, buf)
+        rc = _capi.lib().ccl_fill_holes(ctypes.byref(buf.out), w, h, ctypes.byref(out), None,
+                                        ctypes.c_void_p(ws.data_ptr()), wsb,
+                                        ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        assert rc == 0
+
+    def check(src):
+        of, _ = oracle.fill_holes(src)
+        n = of.n_labels
+        assert oc.cpu().tolist() == [n, of.euler]
+        assert np.array_equal(olab.cpu().numpy(), of.labels)
+        assert np.array_equal(ofeat[:n, 2].cpu().numpy(), of.S)
+        assert np.array_equal(ofeat[:n].view(torch.int32)[:, 0:4].cpu().numpy().astype(np.int64), of.bbox)
+
+    seq()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        seq()
+    for rep in range(3):
+        junk = torch.randn(1 << 20, device=dev).sum()
+        olab.fill_(-7)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        check(img)
+        _say("fill graph replay", rep, "ok", float(junk))
+    t.copy_(1 - t)
+    g.replay()
+    torch.cuda.synchronize()
+    check(1 - img)
