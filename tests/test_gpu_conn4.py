@@ -66,3 +66,7 @@ def test_random_images(seed):
 
 def test_full_size_8192():
     _check(synth.bernoulli_blocks(8192, 8192, 0.5, 1, 102))
+
+
+def test_full_size_structured_16384():
+    _check(synth.structured(16384, 16384, seed=2))

@@ -183,3 +183,7 @@ def test_label_then_fill_captured_in_one_graph():
     g.replay()
     torch.cuda.synchronize()
     check(1 - img)
+
+
+def test_full_size_structured_16384():
+    _check(synth.structured(16384, 16384, seed=0))
