@@ -1017,12 +1017,13 @@ __device__ inline int col_bit(const Work& wk, const ImgDesc& d, int tcol, int y,
 
 template <class T>
 __host__ __device__ inline int64_t merge_items(int w, int h, int ntx, int nty) {
-  // horizontal seams on super-tile row edges (every word), horizontal seams
-  // inside super-tiles (the two edge words of each super-tile column),
-  // vertical seams on super-tile column edges (every row), exterior
+  // horizontal seams on super-tile row edges (every 16-pixel quarter of
+  // every word), horizontal seams inside super-tiles (the two edge words of
+  // each super-tile column), vertical seams on super-tile column edges
+  // (every row), exterior
   const int64_t nwr = (w + 63) / 64, nstx = (ntx + SUP - 1) / SUP;
   const int64_t hb = (nty - 1) / SUP, hi = (nty - 1) - hb, vb = (ntx - 1) / SUP;
-  return hb * nwr + hi * 2 * nstx + vb * h + 2 * nwr + 2 * (int64_t)h;
+  return hb * nwr * 4 + hi * 2 * nstx + vb * h + 2 * nwr + 2 * (int64_t)h;
 }
 
 // ---------------------------------------------------------------------------
@@ -1140,19 +1141,24 @@ __global__ void __launch_bounds__(256) k_border_merge(Src src, Work wk, int64_t 
   constexpr int SW = SUP * T::WPR;  // words per super-tile column
   const int nstx = (d.ntx + SUP - 1) / SUP;
   const int64_t hb = (d.nty - 1) / SUP, hi = (d.nty - 1) - hb, vb = (d.ntx - 1) / SUP;
-  const int64_t nH = hb * nwr + hi * 2 * nstx;
+  const int64_t nH = hb * nwr * 4 + hi * 2 * nstx;
   const int64_t nV = vb * d.h;
   if (i < nH) {  // horizontal seam: bottom row of tile row e-1 above top row of tile row e
     int e, jw;
     bool inner;
-    if (i < hb * nwr) {  // on a super-tile row edge: every word
-      e = SUP * (int)(i / nwr + 1);
-      jw = (int)(i % nwr);
+    u64 part = ~0ull;  // the word's bits this item unites
+    if (i < hb * nwr * 4) {  // on a super-tile row edge: one 16-pixel quarter
+                             // of a word per item (a dense row has up to 32
+                             // union points per word, each a chain of finds)
+      const int64_t iw = i >> 2;
+      e = SUP * (int)(iw / nwr + 1);
+      jw = (int)(iw % nwr);
+      part = 0xFFFFull << (16 * (int)(i & 3));
       inner = false;
     } else {  // inside super-tiles, merged by k_seam_local except for the
               // diagonals that leave a super-tile column at its edge words
-      const int64_t q = (i - hb * nwr) / (2 * nstx);
-      const int r = (int)((i - hb * nwr) % (2 * nstx));
+      const int64_t q = (i - hb * nwr * 4) / (2 * nstx);
+      const int r = (int)((i - hb * nwr * 4) % (2 * nstx));
       e = (int)(q + 1 + q / (SUP - 1));  // the q-th seam index that is not a multiple of SUP
       jw = (r >> 1) * SW + ((r & 1) ? SW - 1 : 0);
       if (jw >= nwr) return;
@@ -1164,7 +1170,9 @@ __global__ void __launch_bounds__(256) k_border_merge(Src src, Work wk, int64_t 
     PairMasks pm = pair_masks<T::FG8>(m0, m1, m0p, m1p, m0n, m1n, valid_mask(jw, d.w), jw > 0,
                                          valid_mask(jw + 1, d.w));
     int xb = jw * 64;
-    u64 m = pm.vert;
+    u64 m = pm.vert & part;
+    pm.da &= part;
+    pm.db &= part;
     if (inner) {  // only the diagonals that cross a super-tile column edge
       m = 0;
       pm.da &= (jw % SW == SW - 1) ? (1ull << 63) : 0ull;
