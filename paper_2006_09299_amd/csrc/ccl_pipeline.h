@@ -1020,10 +1020,11 @@ __host__ __device__ inline int64_t merge_items(int w, int h, int ntx, int nty) {
   // horizontal seams on super-tile row edges (every 16-pixel quarter of
   // every word), horizontal seams inside super-tiles (the two edge words of
   // each super-tile column), vertical seams on super-tile column edges
-  // (every row), exterior
+  // (every row), exterior (top / bottom rows by quarter words, left / right
+  // columns by row)
   const int64_t nwr = (w + 63) / 64, nstx = (ntx + SUP - 1) / SUP;
   const int64_t hb = (nty - 1) / SUP, hi = (nty - 1) - hb, vb = (ntx - 1) / SUP;
-  return hb * nwr * 4 + hi * 2 * nstx + vb * h + 2 * nwr + 2 * (int64_t)h;
+  return hb * nwr * 4 + hi * 2 * nstx + vb * h + 8 * nwr + 2 * (int64_t)h;
 }
 
 // ---------------------------------------------------------------------------
@@ -1218,7 +1219,10 @@ __global__ void __launch_bounds__(256) k_border_merge(Src src, Work wk, int64_t 
     return;
   }
   i -= nV;
-  if (i < 2 * (int64_t)nwr) {  // image top / bottom row: background runs join the exterior
+  if (i < 8 * (int64_t)nwr) {  // image top / bottom row: background runs join the exterior
+                                // (one 16-pixel quarter of a word per item)
+    const int part = (int)(i & 3);
+    i >>= 2;
     bool bottom = i >= nwr;
     int jw = (int)(i % nwr);
     int row = bottom ? d.nty - 1 : 0;
@@ -1227,6 +1231,7 @@ __global__ void __launch_bounds__(256) k_border_merge(Src src, Work wk, int64_t 
     u64 bgp = jw > 0 ? ~seam_bits<T>(wk, d, row, jw - 1, bottom) : 0ull;
     u64 starts = bg & ~((bg << 1) | (bgp >> 63));
     if (jw % T::WPR == 0) starts |= bg & 1ull;  // each tile holds its own piece
+    starts &= 0xFFFFull << (16 * part);
     while (starts) {
       int x = jw * 64 + __builtin_ctzll(starts);
       starts &= starts - 1;
@@ -1234,7 +1239,7 @@ __global__ void __launch_bounds__(256) k_border_merge(Src src, Work wk, int64_t 
     }
     return;
   }
-  i -= 2 * (int64_t)nwr;
+  i -= 8 * (int64_t)nwr;
   if (i < 2 * (int64_t)d.h) {  // image left / right column
     bool right = i >= d.h;
     int y = (int)(i % d.h);
