@@ -1044,8 +1044,12 @@ __device__ inline int lnode_of(const Work& wk, const ImgDesc& d, int tx0, int ty
   return ((ty - ty0) * SUP + (tx - tx0)) * T::BCAP + slot;
 }
 
+// threads per super-tile: its items are chains of dependent loads, so more
+// of them in flight at once
+constexpr int SL_T = 512;
+
 template <class T, class Src>
-__global__ void __launch_bounds__(256) k_seam_local(Src src, Work wk) {
+__global__ void __launch_bounds__(SL_T) k_seam_local(Src src, Work wk) {
   constexpr int NL = SUP * SUP * T::BCAP;
   static_assert(NL < 65536 && NL % 2 == 0, "local node index fits 16 bits");
   __shared__ u32 lpw[NL / 2];  // 16-bit entries; 32-bit words for the links
@@ -1058,7 +1062,7 @@ __global__ void __launch_bounds__(256) k_seam_local(Src src, Work wk) {
   const int tx0 = (int)(ls % nstx) * SUP, ty0 = (int)(ls / nstx) * SUP;
   const int ntxs = d.ntx - tx0 < SUP ? d.ntx - tx0 : SUP;
   const int ntys = d.nty - ty0 < SUP ? d.nty - ty0 : SUP;
-  for (int l = tid; l < NL; l += 256) lp[l] = (u16)l;
+  for (int l = tid; l < NL; l += SL_T) lp[l] = (u16)l;
   __syncthreads();
 
   const int xs0 = tx0 * T::TW;
@@ -1070,7 +1074,7 @@ __global__ void __launch_bounds__(256) k_seam_local(Src src, Work wk) {
   const int y0s = ty0 * T::TH;
   const int rows = (ty0 + ntys) * T::TH < d.h ? (ty0 + ntys) * T::TH - y0s : d.h - y0s;
   const int nv = (ntxs - 1) * rows;
-  for (int it = tid; it < nh + nv; it += 256) {
+  for (int it = tid; it < nh + nv; it += SL_T) {
     if (it < nh) {
       const int e = ty0 + 1 + it / nchk;
       const int x16 = xs0 + (it % nchk) * 16;
@@ -1117,7 +1121,7 @@ __global__ void __launch_bounds__(256) k_seam_local(Src src, Work wk) {
   __syncthreads();
 
   // every node of the super-tile points at its local root
-  for (int l = tid; l < NL; l += 256) {
+  for (int l = tid; l < NL; l += SL_T) {
     const int k = l / T::BCAP, slot = l % T::BCAP;
     const int tx = tx0 + k % SUP, ty = ty0 + k / SUP;
     if (tx - tx0 >= ntxs || ty - ty0 >= ntys) continue;
@@ -2036,7 +2040,7 @@ template <class T, bool HASH, class Src, class Launcher>
 inline void enqueue(Launcher& L, const Src& src, const Work& wk, int64_t tiles, int64_t items, int64_t blocks,
                     int64_t supers) {
   L.launch(k_tile_export<T, Src>, tiles, T::NT, src, wk);
-  L.launch(k_seam_local<T, Src>, supers, 256, src, wk);
+  L.launch(k_seam_local<T, Src>, supers, SL_T, src, wk);
   if (items > 0) L.launch(k_border_merge<T, Src>, (items + 255) / 256, 256, src, wk, items);
   if (HASH) L.launch(k_reduce_roots<T, Src>, (tiles + rh_tiles<T>() - 1) / rh_tiles<T>(), RH_T, src, wk, tiles);
   else L.launch(k_reduce_direct<T, Src>, tiles, 64, src, wk);
