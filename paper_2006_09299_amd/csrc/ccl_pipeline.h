@@ -1264,12 +1264,14 @@ __global__ void __launch_bounds__(256) k_border_merge(Src src, Work wk, int64_t 
 // in an LDS hash table keyed by root and issues one set of atomics per root
 // per flush.
 
-constexpr int RH_CAP = 512;      // LDS hash slots
+constexpr int RH_CAP = 1024;     // LDS hash slots (power of two)
+constexpr int RH_BITS = 10;      // log2(RH_CAP)
+static_assert(1 << RH_BITS == RH_CAP, "hash width");
 // tiles per workgroup: larger groups send fewer atomics to the roots of
 // components that span many tiles (the exterior above all)
 template <class T>
 constexpr int rh_tiles() { return T::N > 4096 ? 64 : 32; }
-constexpr int RH_T = 256;        // threads
+constexpr int RH_T = 512;        // threads: finds of many nodes in flight at once
 constexpr int RH_EMPTY = -1;
 
 struct RootAcc {
@@ -1330,7 +1332,7 @@ __global__ void __launch_bounds__(RH_T) k_reduce_roots(Src src, Work wk, int64_t
       const int32_t key = wk.gkey[node];
       const int r = gfind(wk.gpar, node);  // leaves gpar[node] == r
       if (r != node) {
-        uint32_t hsh = ((uint32_t)r * 2654435761u) >> 23;  // 9 bits
+        uint32_t hsh = ((uint32_t)r * 2654435761u) >> (32 - RH_BITS);
         int slot = (int)hsh;
         for (;;) {
           int k2 = atomicCAS(&tab[slot].key, RH_EMPTY, r);
