@@ -3,26 +3,28 @@
 
 One step = one pass of the whole path over the workload, inputs resident in
 HBM before the timed region:
-  sweep8192      25 images 8192 x 8192, Bernoulli(p) on g x g blocks,
-                 p in {.1,.3,.5,.7,.9} x g in {1,2,4,8,16} (default)
-  structured16384  one 16384 x 16384 image of nested disks + 5% salt
+  structured16384  three 16384 x 16384 images of nested disks + 5% salt
+                   (seeds 0, 1, 2; default: the single-image size the HBM
+                   target is stated on)
+  sweep8192        25 images 8192 x 8192, Bernoulli(p) on g x g blocks,
+                   p in {.1,.3,.5,.7,.9} x g in {1,2,4,8,16}
 Prints one JSON line (stdout); progress goes to stderr.
 
 Per-kernel durations come from HIP events recorded around every kernel of
 every call inside the timed region (ccl_label_traced, on the stream the
 kernels run on).  Algorithmic bytes per image (what the method must move):
-w*h*(1 + 4) + 45 * n_labels + 16, split between the two kernels that move
-them: k_tile_export reads the image (w*h), k_tile_emit writes the label
-image, the tables and the counts (4*w*h + 45 * n_labels + 16); every other
-kernel moves only implementation data (0 algorithmic bytes).  The roofline
-entry is for the dominant kernel (largest average duration): its
-algorithmic bytes per launch / its average duration, against 8 TB/s.
-`traffic` is the kernel's measured HBM bytes per launch from the committed
-rocprofv3 counter summary (profiles/traffic.json, FETCH_SIZE and WRITE_SIZE
-scaled by a plain copy's readings) when that summary was taken from the
-current kernel sources, else null; `traffic_frac` is that measured traffic
-over the kernel's average duration, against 8 TB/s.  `hbm_copy_ceiling` is
-the best rate of a plain 1 GiB device-to-device copy on the same GPU.
+B = w*h*(1 + 4) + 45 * n_labels + 16 (read the image, write the label image
+and one 45-byte row of the feature / parent / colour tables per label).
+`roofline` is the dominant kernel (largest average duration): B per image
+(one image per launch) / its average duration, against 8 TB/s; beside it,
+`kernel_own` credits the kernel only with the bytes it moves itself
+(k_tile_export reads the image, k_tile_emit writes the rest).  `path_hbm` is
+B over the whole path's time per image.  `traffic` is the kernel's measured
+HBM bytes per launch from the committed rocprofv3 counter summary
+(profiles/traffic.json, FETCH_SIZE and WRITE_SIZE scaled by a plain copy's
+readings) when that summary was taken from the current kernel sources, else
+null.  `hbm_copy_ceiling` is the best rate of a plain 1 GiB device-to-device
+copy on the same GPU.
 """
 from __future__ import annotations
 
@@ -118,8 +120,39 @@ def make_workload(name: str):
             say(f"  generated 8192^2 p={p} g={g} seed={seed}")
         return imgs
     if name == "structured16384":
-        return [(("structured", 0), synth.structured(16384, 16384, seed=0))]
+        imgs = []
+        for seed in STRUCTURED_SEEDS:
+            imgs.append((("structured", seed), synth.structured(16384, 16384, seed=seed)))
+            say(f"  generated 16384^2 structured seed={seed}")
+        return imgs
     raise SystemExit(f"unknown workload {name}")
+
+
+STRUCTURED_SEEDS = (0, 1, 2)
+WORKLOAD_TEXT = {
+    "structured16384": "16384x16384 uint8 nested disks/annuli (radii 4..2000 px, depth 1..8) + 5% salt, "
+                       "seeds 0-2, one image per launch",
+    "sweep8192": "8192x8192 uint8 Bernoulli(p) on g x g blocks, p in {.1,.3,.5,.7,.9} x g in {1,2,4,8,16}, "
+                 "one image per launch",
+}
+
+
+def host_cpu():
+    """Model name and usable cores of the host that runs the oracle."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"model": model, "usable_cores": usable, "logical_cpus": os.cpu_count()}
 
 
 def run_gpu(work, steps: int, warmup: int):
@@ -193,17 +226,117 @@ def run_gpu(work, steps: int, warmup: int):
 
 
 def roofline(r, workload: str):
-    """Roofline entry of the dominant kernel of a run_gpu result."""
+    """Roofline entry of the dominant kernel of a run_gpu result: the path's
+    algorithmic bytes per image (one image per launch) over the kernel's
+    average duration; `kernel_own` counts only the bytes the kernel itself
+    moves."""
     k = max(r["kernel_avg_ms"], key=r["kernel_avg_ms"].get)
     ms = r["kernel_avg_ms"][k]
-    gbs = r["kernel_alg_bytes"][k] / (ms / 1e3) / 1e9
+    b_launch = r["alg_bytes_per_step"] / len(r["counts"])
+    gbs = b_launch / (ms / 1e3) / 1e9
+    own = r["kernel_alg_bytes"][k] / (ms / 1e3) / 1e9
     traffic = measured_traffic(workload, k)
     out = {"bound": "hbm", "kernel": k, "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
-           "alg_bytes_per_launch": int(r["kernel_alg_bytes"][k]), "avg_ms": round(ms, 5)}
+           "alg_bytes_per_launch": int(b_launch), "avg_ms": round(ms, 5),
+           "kernel_own": {"alg_bytes_per_launch": int(r["kernel_alg_bytes"][k]), "GBs": round(own, 1),
+                          "frac": round(own / HBM_PEAK_GBS, 4)}}
     if traffic is not None:  # measured HBM bytes over the same duration
         out["traffic_frac"] = round(traffic / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
     return out
+
+
+def summarize(r, workload: str):
+    ms = r["total_ms"] / r["steps"] / len(r["counts"])
+    px = r["pixels_per_step"] / len(r["counts"])
+    b = r["alg_bytes_per_step"] / len(r["counts"])
+    return {"Gpixel_s": round(px / (ms / 1e3) / 1e9, 3), "ms_per_image": round(ms, 4),
+            "path_hbm": {"alg_GBs": round(b / (ms / 1e3) / 1e9, 1), "frac": round(b / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
+            "roofline": roofline(r, workload), "launches_per_image": len(r["kernel_avg_ms"]),
+            "kernel_avg_ms": {k: round(v, 5) for k, v in r["kernel_avg_ms"].items()}}
+
+
+def cold_warm(work, reps: int = 1):
+    """Whole-path time per image with the caches cold (1 GiB written between
+    images, so neither L2 nor the 256 MB Infinity Cache holds the image or
+    the workspace) and warm (the same image again right after)."""
+    import torch
+    import paper_2006_09299_amd as ccl
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    h, w = work[0][1].shape
+    buf = ccl.Buffers(w, h, w * h // 4 + 1024, dev)
+    flush = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    cold, warm = [], []
+    for _, img in work:
+        t = torch.from_numpy(img).to(dev)
+        ccl.launch(t, buf)  # module load, first touch of the buffers
+        for _ in range(reps):
+            flush.fill_(1)
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            e[0].record(stream)
+            ccl.launch(t, buf)
+            e[1].record(stream)
+            e[2].record(stream)
+            ccl.launch(t, buf)
+            e[3].record(stream)
+            torch.cuda.synchronize()
+            cold.append(e[0].elapsed_time(e[1]))
+            warm.append(e[2].elapsed_time(e[3]))
+        del t
+    del flush, buf
+    cold.sort()
+    warm.sort()
+    med = lambda v: v[len(v) // 2]
+    gps = lambda ms: round(w * h / (ms / 1e3) / 1e9, 2)
+    return {"images": len(work), "flush_bytes": 1 << 30,
+            "cold": {"median_ms": round(med(cold), 4), "Gpixel_s_median": gps(med(cold)),
+                     "Gpixel_s_total": round(w * h * len(cold) / (sum(cold) / 1e3) / 1e9, 2)},
+            "warm": {"median_ms": round(med(warm), 4), "Gpixel_s_median": gps(med(warm)),
+                     "Gpixel_s_total": round(w * h * len(warm) / (sum(warm) / 1e3) / 1e9, 2)}}
+
+
+def run_c1(reps: int = 400):
+    """512 x 512, p = 0.5, seed 0: one image per launch sequence, eager and
+    replayed from a captured HIP graph."""
+    import torch
+    import synth
+    import paper_2006_09299_amd as ccl
+    dev = torch.device("cuda:0")
+    img = synth.bernoulli_blocks(512, 512, 0.5, 1, 0)
+    t = torch.from_numpy(img).to(dev)
+    buf = ccl.Buffers(512, 512, 512 * 512 // 4 + 1024, dev)
+    for _ in range(5):
+        ccl.launch(t, buf)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        ccl.launch(t, buf)
+    b.record()
+    torch.cuda.synchronize()
+    eager_ms = a.elapsed_time(b) / reps
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        ccl.launch(t, buf)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        g.replay()
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        g.replay()
+    b.record()
+    torch.cuda.synchronize()
+    graph_ms = a.elapsed_time(b) / reps
+    n = int(buf.counts[0].item())
+    px = 512 * 512
+    return {"shape": [512, 512], "p": 0.5, "seed": 0, "n_labels": n,
+            "eager_us_per_image": round(eager_ms * 1e3, 2), "eager_Gpixel_s": round(px / (eager_ms / 1e3) / 1e9, 2),
+            "graph_us_per_image": round(graph_ms * 1e3, 2), "graph_Gpixel_s": round(px / (graph_ms / 1e3) / 1e9, 2),
+            "path_hbm_frac_graph": round(algorithmic_bytes(512, 512, n) / (graph_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
 def copy_ceiling(mib: int = 1024, reps: int = 5):
@@ -225,9 +358,10 @@ def copy_ceiling(mib: int = 1024, reps: int = 5):
     return {"GBs": round(gbs, 1), "frac_of_peak": round(gbs / HBM_PEAK_GBS, 4), "bytes_copied": n}
 
 
-def run_batch(n_images: int, steps: int, warmup: int):
+def run_batch(n_images: int, steps: int, warmup: int, host_out=None):
     """The uneven batch: one captured launch sequence per step (graph
-    replay), autotuned variant; then the same images one launch per image."""
+    replay), autotuned variant; then the same images one launch per image.
+    host_out (a list), if given, receives the host images."""
     import numpy as np
     import torch
     import synth
@@ -238,7 +372,10 @@ def run_batch(n_images: int, steps: int, warmup: int):
     specs = synth.batch_specs(n_images)
     imgs = []
     for i, sp in enumerate(specs):
-        imgs.append(torch.from_numpy(sp.make()).to(dev))
+        im = sp.make()
+        if host_out is not None:
+            host_out.append(im)
+        imgs.append(torch.from_numpy(im).to(dev))
         if (i + 1) % 1024 == 0:
             say(f"  generated {i + 1}/{n_images} batch images")
     px = sum(sp.pixels for sp in specs)
@@ -283,7 +420,9 @@ def run_batch(n_images: int, steps: int, warmup: int):
            "tile": list(ccl.variant_info(variant)[:2]), "hash_reduce": ccl.variant_info(variant)[2],
            "threads": ccl.variant_info(variant)[3],
            "graph_ms_per_batch": round(batch_ms, 3), "Gpixel_s": round(px / (batch_ms / 1e3) / 1e9, 2),
-           "batch_latency_ms_p50": round(lat_ms[len(lat_ms) // 2], 3), "batch_latency_ms_max": round(lat_ms[-1], 3),
+           "batch_latency_ms_p50": round(lat_ms[len(lat_ms) // 2], 3),
+           "batch_latency_ms_p99": round(lat_ms[min(len(lat_ms) - 1, int(0.99 * len(lat_ms)))], 3),
+           "batch_latency_ms_max": round(lat_ms[-1], 3),
            "per_image_loop_ms": round(loop_ms, 3),
            "per_image_loop_Gpixel_s": round(px / (loop_ms / 1e3) / 1e9, 2),
            "speedup_vs_loop": round(loop_ms / batch_ms, 2)}
@@ -291,23 +430,41 @@ def run_batch(n_images: int, steps: int, warmup: int):
     return out
 
 
-def run_serve(n_requests: int, rate_hz: float = 2000.0, warmup_s: float = 1.0, pool_images: int = 128,
-              budget_gib: int = 48, batched: bool = True):
-    """Open-loop Poisson request stream through the serving loop.  Requests
-    draw their image from a pool of pre-generated host images with the
-    stream's size / density distribution (sides log-uniform in [256, 8192]).
+def serve_sources(sweep):
+    """Pinned host copies of the sweep images with g in {1, 4}: the serving
+    leg crops every request out of one of them."""
+    import torch
+    src = {}
+    for (p, g, _seed), img in sweep:
+        if g in (1, 4):
+            src[(p, g)] = torch.from_numpy(img).pin_memory()
+    return src
+
+
+def run_serve(n_requests: int, sources, rate_hz: float = 2000.0, warmup_s: float = 1.0, budget_gib: int = 48,
+              batched: bool = True):
+    """Open-loop Poisson request stream through the serving loop.  Every
+    request has the stream's own size (sides log-uniform in [256, 8192]) and
+    is a crop, at a random offset, of the 8192^2 sweep image with the same
+    granularity and the density nearest its own (strided host rows, pinned).
     Latency = completion observed - scheduled arrival."""
     import numpy as np
-    import torch
     import synth
     from paper_2006_09299_amd.serve import Server
 
     warm = int(warmup_s * rate_hz)
     stream = synth.serve_stream(n_requests + warm, rate_hz=rate_hz)
+    ps = sorted({p for p, _ in sources})
+    rng = np.random.default_rng(12)
     host = []
-    for i in range(pool_images):
-        host.append(torch.from_numpy(stream[i].spec.make()).pin_memory())
-    say(f"  serve: {pool_images} pooled images, mean {np.mean([t.numel() for t in host]) / 1e6:.2f} Mpx")
+    for rq in stream:
+        sp = rq.spec
+        p = min(ps, key=lambda q: abs(q - sp.p))
+        src = sources[(p, sp.g)]
+        y0 = int(rng.integers(0, src.shape[0] - sp.h + 1))
+        x0 = int(rng.integers(0, src.shape[1] - sp.w + 1))
+        host.append(src[y0:y0 + sp.h, x0:x0 + sp.w])
+    say(f"  serve: {len(host)} requests, mean {np.mean([t.numel() for t in host]) / 1e6:.2f} Mpx")
     srv = Server(budget_gib << 30, max_slots=512 if batched else 1, streams=4 if batched else 1,
                  max_batch=64 if batched else 1)
     lat, px_done, t_first, t_last, qmax = [], 0, None, None, 0
@@ -316,7 +473,7 @@ def run_serve(n_requests: int, rate_hz: float = 2000.0, warmup_s: float = 1.0, p
     while i < len(stream) or not srv.idle():
         now = srv.now() - start
         while i < len(stream) and stream[i].arrival_s <= now:
-            srv.submit(i, host[i % pool_images], arrival=start + stream[i].arrival_s)
+            srv.submit(i, host[i], arrival=start + stream[i].arrival_s)
             i += 1
         for r in srv.step():
             if r.rid >= warm:
@@ -409,16 +566,13 @@ def run_widened(work, reps: int = 3):
             "fg4_bg8": {"Gpixel_s": gps(c4_ms), "ms_per_image": round(c4_ms / (px / (w * h)), 4)}}
 
 
-def cpu_baseline(work, budget_s: float = 15.0):
-    """The oracle as it stands, single-threaded, on a bounded sample."""
+def cpu_baseline(work, budget_s: float = 40.0):
+    """The oracle as it stands, one thread, on the headline workload's images
+    (one pass each, until the time budget is spent)."""
     import oracle
     oracle.build(force=False)
-    order = list(range(len(work)))
-    if len(work) > 3:  # spread the sample over densities and granularities
-        order = [len(work) // 2, 0, len(work) - 1] + [i for i in range(len(work)) if i not in (0, len(work) // 2, len(work) - 1)]
     px, secs, used = 0, 0.0, []
-    for i in order:
-        tag, img = work[i]
+    for tag, img in work:
         t0 = time.perf_counter()
         oracle.label(img)
         secs += time.perf_counter() - t0
@@ -428,7 +582,52 @@ def cpu_baseline(work, budget_s: float = 15.0):
         if secs >= budget_s:
             break
     return dict(value=px / secs / 1e9, unit="Gpixel/s", cores=1, kind="oracle",
-                sample=f"{len(used)} of {len(work)} workload images {used}, one thread, {secs:.1f} s")
+                sample=f"{len(used)} of {len(work)} workload images {used}, one pass each, one thread, "
+                       f"{secs:.1f} s",
+                host=host_cpu())
+
+
+def oracle_timings(sweep, batch_host):
+    """The oracle on the other configurations: 512 x 512 (p = 0.5, seed 0;
+    median of 5, in ms), every image of the 8192^2 sweep once (one thread),
+    and the 4096-image uneven batch over all usable host cores (threads; the
+    oracle's C call runs without the interpreter lock)."""
+    import concurrent.futures as cf
+    import oracle
+    import synth
+    oracle.build(force=False)
+    out = {"host": host_cpu()}
+    img = synth.bernoulli_blocks(512, 512, 0.5, 1, 0)
+    ts = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        oracle.label(img)
+        ts.append(time.perf_counter() - t0)
+    ts.sort()
+    out["c1_512"] = {"median_ms": round(ts[2] * 1e3, 3), "Mpixel_s": round(img.size / ts[2] / 1e6, 2), "cores": 1}
+    per, secs, px = {}, 0.0, 0
+    for tag, im in sweep:
+        t0 = time.perf_counter()
+        oracle.label(im)
+        dt = time.perf_counter() - t0
+        per[f"p{tag[0]}_g{tag[1]}"] = round(dt * 1e3, 1)
+        secs += dt
+        px += im.size
+    say(f"  oracle sweep: {secs:.1f} s for {len(sweep)} images")
+    out["sweep8192"] = {"images": len(sweep), "total_s": round(secs, 2), "Mpixel_s": round(px / secs / 1e6, 2),
+                        "cores": 1, "ms_per_image": per}
+    if batch_host:
+        cores = out["host"]["usable_cores"]
+        px = sum(im.size for im in batch_host)
+        t0 = time.perf_counter()
+        with cf.ThreadPoolExecutor(cores) as ex:
+            for _ in ex.map(oracle.label, batch_host):
+                pass
+        dt = time.perf_counter() - t0
+        say(f"  oracle batch: {dt:.1f} s on {cores} threads")
+        out["batch4096"] = {"images": len(batch_host), "total_s": round(dt, 2), "Mpixel_s": round(px / dt / 1e6, 2),
+                            "cores": cores}
+    return out
 
 
 def main():
@@ -436,9 +635,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="sweep8192", choices=["sweep8192", "structured16384"])
+    ap.add_argument("--workload", default="structured16384", choices=["structured16384", "sweep8192"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-also", action="store_true", help="skip the secondary structured16384 measurement")
+    ap.add_argument("--no-also", action="store_true", help="only the headline workload")
     ap.add_argument("--serve-requests", type=int, default=20000, help="measured requests of the serving leg")
     ap.add_argument("--fill-only", action="store_true",
                     help="only the hole-filling / features-only leg on the sweep images (for profiling)")
@@ -467,13 +666,13 @@ def main():
     say(f"bench: workload {args.workload}, steps {args.steps}, warmup {args.warmup}")
     work = make_workload(args.workload)
     r = run_gpu(work, args.steps, args.warmup)
+    head = summarize(r, args.workload)
     ms_step = r["total_ms"] / r["steps"]
-    gpx = r["pixels_per_step"] / (ms_step / 1e3) / 1e9
-    path_gbs = r["alg_bytes_per_step"] / (ms_step / 1e3) / 1e9
-    say(f"  {gpx:.1f} Gpixel/s, {ms_step:.3f} ms/step, kernels {json.dumps({k: round(v, 4) for k, v in r['kernel_avg_ms'].items()})}")
+    say(f"  {head['Gpixel_s']} Gpixel/s, {ms_step:.3f} ms/step, kernels {json.dumps(head['kernel_avg_ms'])}")
+    import paper_2006_09299_amd as ccl
     out = {
         "metric": "Gpixel/s labeling+features+tree+Euler (1 GPU)",
-        "value": round(gpx, 3),
+        "value": head["Gpixel_s"],
         "unit": "Gpixel/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -484,45 +683,59 @@ def main():
         "vs_baseline": None,
         "dtype": "u8",
         "data": "synthetic",
-        "config": {"workload": args.workload, "images_per_step": len(work),
-                   "shape": list(work[0][1].shape), "tile": list(__import__("paper_2006_09299_amd").tile_shape())},
-        "roofline": roofline(r, args.workload),
-        "path_hbm": {"alg_GBs": round(path_gbs, 1), "frac": round(path_gbs / HBM_PEAK_GBS, 4)},
+        "config": {"workload": WORKLOAD_TEXT[args.workload], "name": args.workload, "images_per_step": len(work),
+                   "shape": list(work[0][1].shape), "tile": list(ccl.tile_shape())},
+        "roofline": head["roofline"],
+        "path_hbm": head["path_hbm"],
+        "ms_per_image": head["ms_per_image"],
+        "launches_per_image": head["launches_per_image"],
         "hbm_copy_ceiling": copy_ceiling(),
-        "kernel_avg_ms": {k: round(v, 5) for k, v in r["kernel_avg_ms"].items()},
+        "kernel_avg_ms": head["kernel_avg_ms"],
     }
-    if args.workload == "sweep8192" and not args.no_also:
-        say("bench: secondary workload structured16384")
-        w2 = make_workload("structured16384")
-        r2 = run_gpu(w2, max(2, args.steps), 1)
-        ms2 = r2["total_ms"] / r2["steps"]
-        out["also"] = {"structured16384": {
-            "Gpixel_s": round(r2["pixels_per_step"] / (ms2 / 1e3) / 1e9, 3), "ms_per_image": round(ms2, 4),
-            "path_hbm_frac": round(r2["alg_bytes_per_step"] / (ms2 / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-            "roofline": roofline(r2, "structured16384"),
-            "kernel_avg_ms": {k: round(v, 5) for k, v in r2["kernel_avg_ms"].items()}}}
-    if args.workload == "sweep8192" and not args.no_also:
-        say("bench: hole filling, features-only mode and the 4/8 connectivity pair on the same images")
-        fx = run_widened(work)
+    also = {}
+    sweep, batch_host = None, []
+    if not args.no_also:
+        if args.workload == "sweep8192":
+            sweep = work
+            say("bench: secondary workload structured16384")
+            w2 = make_workload("structured16384")
+            also["structured16384"] = summarize(run_gpu(w2, max(2, args.steps), 1), "structured16384")
+            del w2
+        else:
+            say("bench: secondary workload sweep8192")
+            sweep = make_workload("sweep8192")
+            also["sweep8192"] = summarize(run_gpu(sweep, max(2, min(args.steps, 5)), 1), "sweep8192")
+        say("bench: 8192^2 sweep, caches cold and warm")
+        also["sweep8192_cold_warm"] = cold_warm(sweep)
+        say(f"  {json.dumps(also['sweep8192_cold_warm'])}")
+        say("bench: 512^2, eager and graph-replayed")
+        also["c1_512"] = run_c1()
+        say(f"  {json.dumps(also['c1_512'])}")
+        say("bench: hole filling, features-only mode and the 4/8 connectivity pair on the sweep images")
+        fx = run_widened(sweep)
         say(f"  {json.dumps(fx)}")
-        out.setdefault("also", {})["widened_sweep8192"] = fx
-    if args.workload == "sweep8192" and not args.no_also:
-        say("bench: secondary workload batch4096")
-        out.setdefault("also", {})["batch4096"] = run_batch(4096, max(3, args.steps), 1)
-    if args.workload == "sweep8192" and not args.no_also:
+        also["widened_sweep8192"] = fx
+        say("bench: batch4096")
+        also["batch4096"] = run_batch(4096, max(3, args.steps), 1, host_out=batch_host)
         say("bench: serving (continuous batching), then one request per launch")
-        sv = run_serve(args.serve_requests)
+        src = serve_sources(sweep)
+        sv = run_serve(args.serve_requests, src)
         say(f"  serve: {json.dumps(sv)}")
-        sv1 = run_serve(min(args.serve_requests, 4000), batched=False)
+        sv1 = run_serve(min(args.serve_requests, 4000), src, batched=False)
         say(f"  serve, one request per launch: {json.dumps(sv1)}")
         # offered load far above what one GPU can take: the server's capacity
-        sv2 = run_serve(args.serve_requests, rate_hz=40000.0, warmup_s=0.05)
+        sv2 = run_serve(args.serve_requests, src, rate_hz=40000.0, warmup_s=0.05)
         say(f"  serve, overloaded: {json.dumps(sv2)}")
-        out.setdefault("also", {})["serve"] = {"continuous_batching": sv, "one_request_per_launch": sv1,
-                                               "overloaded_40k_req_s": sv2}
+        also["serve"] = {"continuous_batching": sv, "one_request_per_launch": sv1, "overloaded_40k_req_s": sv2}
+        del src
     if not args.no_cpu_baseline:
-        say("bench: cpu baseline (oracle)")
+        say("bench: cpu baseline (oracle) on the headline workload")
         out["cpu_baseline"] = cpu_baseline(work)
+        if sweep is not None:
+            say("bench: oracle on 512^2, the sweep and the batch")
+            also["oracle"] = oracle_timings(sweep, batch_host)
+    if also:
+        out["also"] = also
     print(json.dumps(out), flush=True)
 
 

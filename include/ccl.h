@@ -136,6 +136,17 @@ int ccl_label_v(const uint8_t *img, int32_t w, int32_t h, int64_t pitch, const c
 /* Batch: `n` images labeled by one sequence of launches in which every
  * kernel covers every tile of every image (sizes may all differ).
  *
+ * Why the batch call takes the host array `imgs` and a `variant` besides the
+ * device descriptors: the grid of every kernel is a batch total (tiles,
+ * super-tiles, seam work items, scan blocks) that depends on the compiled
+ * tile shape of the variant.  Computing it on the host from `imgs` needs no
+ * device-to-host copy and no synchronisation, so the call stays asynchronous
+ * and can be captured into a hipGraph.  The device block is what the kernels
+ * read; it must be the one ccl_batch_prepare wrote for the same `imgs` and
+ * `variant`.  Every descriptor carries a digest of the launch shape it was
+ * placed for (variant shape and batch totals); kernels of another shape skip
+ * it, and the image's counts[0] is set to -1 (nothing else is written).
+ *
  * [host] ccl_batch_sizes: bytes of the device descriptor block and of the
  * workspace for the images described in `imgs` [host] under `variant`. */
 int ccl_batch_sizes(const ccl_image_t *imgs, int32_t n, int32_t variant, size_t *desc_bytes, size_t *ws_bytes);
@@ -146,9 +157,11 @@ int ccl_batch_sizes(const ccl_image_t *imgs, int32_t n, int32_t variant, size_t 
 int ccl_batch_prepare(const ccl_image_t *imgs, int32_t n, int32_t variant, void *host_desc, size_t desc_bytes);
 
 /* Enqueue the batch.  `dev_desc` [device] holds the block written by
- * ccl_batch_prepare for the same `imgs` [host] and `variant`.  Capturable in
- * a hipGraph and replayable: it allocates nothing, never synchronises and
- * records no memset (every kernel writes all the scratch it reads). */
+ * ccl_batch_prepare for the same `imgs` [host] and `variant` (a block placed
+ * for other images or another variant is refused image by image on the
+ * device: counts[0] = -1).  Capturable in a hipGraph and replayable: it
+ * allocates nothing, never synchronises and records no memset (every kernel
+ * writes all the scratch it reads). */
 int ccl_label_batch(const ccl_image_t *imgs, int32_t n, int32_t variant, const void *dev_desc, void *ws,
                     size_t ws_bytes, void *stream);
 
@@ -181,7 +194,12 @@ int ccl_fill_holes(const ccl_outputs_t *in, int32_t w, int32_t h, const ccl_outp
 
 /* Serving: continuous batching over ccl_label_batch.  The paper labels one
  * image at a time; this front end runs the same path for a stream of requests
- * of any sizes.  Requests are admitted in arrival order as soon as a slot and
+ * of any sizes.  The calls take a caller-owned device pool (so that the
+ * library allocates no device memory and admission is an exact test of a
+ * request's footprint against that pool), name requests by a caller tag at
+ * submission, and report them through a non-blocking poll that hands back
+ * device pointers into the pool, so results stay on the device until the
+ * caller releases them.  Requests are admitted in arrival order as soon as a slot and
  * device memory for their whole footprint are free; everything admitted at one
  * poll forms a micro-batch, launched on the next idle one of the server's
  * streams, so that newly admitted work overlaps earlier micro-batches.
@@ -212,8 +230,9 @@ typedef struct {
 /* A finished request. */
 typedef struct {
   int64_t tag;
-  int32_t status;    /* CCL_OK, or CCL_ENOSPC: the tables this image needs do not fit the pool
-                        (n_labels holds the number of labels; no outputs) */
+  int32_t status;    /* CCL_OK; CCL_ENOSPC: the tables this image needs do not fit the pool
+                        (n_labels holds the number of labels; no outputs); or the code a batch
+                        entry point refused its micro-batch with (no outputs) */
   int32_t w, h;
   int32_t launches;  /* 1, or 2 when the first table capacity was too small and the request ran
                         again with exactly n_labels entries */

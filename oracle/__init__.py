@@ -104,7 +104,10 @@ def label(img: np.ndarray, lib=None, fg8: bool = True) -> Result:
     lib = lib if lib is not None else _load()
     labels = np.empty((h, w), dtype=np.int32)
     euler = np.zeros(1, dtype=np.int64)
-    cap = 16
+    # first table capacity: a quarter of the pixels covers every image of the
+    # workloads but checkerboard-like ones; a larger count is reported and
+    # the call is repeated with the exact size
+    cap = h * w // 4 + 16
     while True:
         feat = np.empty((cap, 7), dtype=np.int64)
         parent = np.empty(cap, dtype=np.int32)

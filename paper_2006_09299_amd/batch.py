@@ -110,6 +110,8 @@ class BatchPlan:
         out = []
         for i in range(self.n):
             nl, eu = int(counts[i, 0]), int(counts[i, 1])
+            if nl < 0:  # the kernels refused descriptors placed for another launch shape
+                raise _capi.CclError(_capi.CCL_EINVAL, f"image {i}: descriptors do not match the launch")
             if nl > self.caps[i]:
                 raise _capi.CclError(_capi.CCL_ECAPACITY, f"image {i}: {nl} labels > cap {self.caps[i]}")
             out.append(Result(self.labels[i], self.features[i][:nl], self.parent[i][:nl], self.color[i][:nl],

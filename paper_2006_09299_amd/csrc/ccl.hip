@@ -85,7 +85,7 @@ ccl::ImgDesc to_desc(const uint8_t* img, int32_t w, int32_t h, int64_t pitch, co
   d.counts = out->counts;
   d.flags = 0;
   if ((reinterpret_cast<uintptr_t>(img) & 15) == 0 && (pitch & 15) == 0) d.flags |= ccl::DF_VEC_IN;
-  if ((reinterpret_cast<uintptr_t>(out->labels) & 15) == 0 && (w & 3) == 0) d.flags |= ccl::DF_VEC_LAB;
+  if (out->labels && (reinterpret_cast<uintptr_t>(out->labels) & 15) == 0 && (w & 3) == 0) d.flags |= ccl::DF_VEC_LAB;
   return d;
 }
 
@@ -94,7 +94,21 @@ struct Totals {
   bool too_big() const { return nodes >= INT32_MAX || tiles >= INT32_MAX || blocks >= INT32_MAX; }
 };
 
-// geometry of a batch under variant Vt; fills ds (may be null)
+// digest of a batch's launch shape: the variant's compile-time shape and the
+// totals the descriptors were placed for (FNV-1a over the values)
+template <class Vt>
+uint32_t batch_check(const Totals& t, int32_t n) {
+  using T = typename Vt::T;
+  const int64_t v[] = {T::TH, T::TW, T::NT, Vt::hash ? 1 : 0, T::FG8 ? 1 : 0, t.tiles, t.nodes, t.cells,
+                       t.blocks, t.items, t.supers, n};
+  uint32_t h = 2166136261u;
+  for (int64_t x : v)
+    for (int b = 0; b < 8; b++) h = (h ^ (uint32_t)((uint64_t)x >> (8 * b) & 0xFF)) * 16777619u;
+  return h;
+}
+
+// geometry of a batch under variant Vt; fills ds (may be null) with the
+// batch's check digest
 template <class Vt>
 int place_batch(const ccl_image_t* imgs, int32_t n, ccl::ImgDesc* ds, Totals& t) {
   for (int32_t i = 0; i < n; i++) {
@@ -104,7 +118,12 @@ int place_batch(const ccl_image_t* imgs, int32_t n, ccl::ImgDesc* ds, Totals& t)
     ccl::place_image<typename Vt::T>(d, t.tiles, t.nodes, t.cells, t.blocks, t.items, t.supers);
     if (ds) ds[i] = d;
   }
-  return t.too_big() ? CCL_ETOOBIG : CCL_OK;
+  if (t.too_big()) return CCL_ETOOBIG;
+  if (ds) {
+    const uint32_t c = batch_check<Vt>(t, n);
+    for (int32_t i = 0; i < n; i++) ds[i].check = c;
+  }
+  return CCL_OK;
 }
 
 int label_one(const uint8_t* img, int32_t w, int32_t h, int64_t pitch, const ccl_outputs_t* out, void* ws,
@@ -301,7 +320,7 @@ int ccl_label_batch(const ccl_image_t* imgs, int32_t n, int32_t variant, const v
     if (ws_bytes < L.bytes) return CCL_ENOSPC;
     ccl::Work wk = ccl::make_work(L, ws);
     HipLauncher hl{static_cast<hipStream_t>(stream)};
-    ccl::ManyImages src{static_cast<const ccl::ImgDesc*>(dev_desc), n};
+    ccl::ManyImages src{static_cast<const ccl::ImgDesc*>(dev_desc), n, batch_check<Vt>(t, n)};
     ccl::enqueue<T, Vt::hash>(hl, src, wk, t.tiles, t.items, t.blocks, t.supers);
     return hl.err == hipSuccess ? CCL_OK : CCL_EHIP;
   });

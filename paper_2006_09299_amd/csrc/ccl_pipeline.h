@@ -98,6 +98,10 @@ struct ImgDesc {
   int64_t it0;       // first border-merge work item
   int64_t nit;       // border-merge work items
   int64_t s0;        // first super-tile (SUP x SUP tiles) of this image
+  uint32_t check;    // batches: digest of the variant and the batch totals the
+                     // descriptor was placed for (kernels of another launch
+                     // shape leave it alone)
+  uint32_t pad_;
 };
 
 enum { DF_VEC_IN = 1, DF_VEC_LAB = 2 };
@@ -767,11 +771,13 @@ struct OneImage {
   __device__ const ImgDesc& by_index(int64_t) const { return d; }
   __device__ const ImgDesc& by_super(int64_t) const { return d; }
   __device__ int64_t count() const { return 1; }
+  __device__ bool ok(const ImgDesc&) const { return true; }
 };
 
 struct ManyImages {
   const ImgDesc* ds;
   int32_t n;
+  uint32_t check;  // what every descriptor of this launch must carry
   // last descriptor whose field `first` is <= v (descriptors sorted by it)
   template <class Get>
   __device__ const ImgDesc& search(int64_t v, Get get) const {
@@ -789,6 +795,7 @@ struct ManyImages {
   __device__ const ImgDesc& by_index(int64_t i) const { return ds[i]; }
   __device__ const ImgDesc& by_super(int64_t v) const { return search(v, [](const ImgDesc& d) { return d.s0; }); }
   __device__ int64_t count() const { return n; }
+  __device__ bool ok(const ImgDesc& d) const { return d.check == check; }
 };
 
 template <class T>
@@ -976,6 +983,10 @@ __global__ void __launch_bounds__(T::NT) k_tile_export(Src src, Work wk) {
   __shared__ Acc bacc[T::BCAP];
   const int64_t gt = blockIdx.x;
   const ImgDesc& d = src.by_tile(gt);
+  if (!src.ok(d)) {  // placed for another variant or batch: flag the image
+    if (threadIdx.x == 0 && d.counts) d.counts[0] = -1;
+    return;
+  }
   const TileGeom g = tile_geom<T>(d, gt);
   TileFetch<T> f;
   tile_fetch<T>(f, d, g);
@@ -1057,6 +1068,7 @@ __global__ void __launch_bounds__(SL_T) k_seam_local(Src src, Work wk) {
   const int tid = threadIdx.x;
   const int64_t gs = blockIdx.x;
   const ImgDesc& d = src.by_super(gs);
+  if (!src.ok(d)) return;
   const int64_t ls = gs - d.s0;
   const int nstx = (d.ntx + SUP - 1) / SUP;
   const int tx0 = (int)(ls % nstx) * SUP, ty0 = (int)(ls / nstx) * SUP;
@@ -1140,6 +1152,7 @@ __global__ void __launch_bounds__(256) k_border_merge(Src src, Work wk, int64_t 
   const int64_t gi = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (gi >= total) return;
   const ImgDesc& d = src.by_item(gi);
+  if (!src.ok(d)) return;
   int64_t i = gi - d.it0;
   const int nwr = (d.w + 63) >> 6;
   const int ext = (int)d.node0;
@@ -1307,7 +1320,7 @@ __global__ void __launch_bounds__(RH_T) k_reduce_roots(Src src, Work wk, int64_t
     if (tid < ntl) {
       const int64_t gt = t0 + tid;
       const ImgDesc& d = src.by_tile(gt);
-      c = wk.nbt[gt];
+      c = src.ok(d) ? wk.nbt[gt] : 0;
       tbase[tid] = tile_node_base<T>(d, gt - d.tile0);
     }
     int inc = c;
@@ -1388,6 +1401,7 @@ template <class T, class Src>
 __global__ void __launch_bounds__(64) k_reduce_direct(Src src, Work wk) {
   const int64_t gt = blockIdx.x;
   const ImgDesc& d = src.by_tile(gt);
+  if (!src.ok(d)) return;
   const int64_t nbase = tile_node_base<T>(d, gt - d.tile0);
   const int nb = wk.nbt[gt];
   for (int i = threadIdx.x; i < nb; i += 64) {
@@ -1417,6 +1431,7 @@ __global__ void __launch_bounds__(64) k_leaders(Src src, Work wk) {
   __shared__ u32 cnt[T::TH];
   const int64_t gt = blockIdx.x;
   const ImgDesc& d = src.by_tile(gt);
+  if (!src.ok(d)) return;
   const int64_t lt = gt - d.tile0;
   const int tx = (int)(lt % d.ntx), ty = (int)(lt / d.ntx);
   const int y0 = ty * T::TH;
@@ -1486,6 +1501,7 @@ __global__ void __launch_bounds__(SCAN_T) k_scan_reduce(Src src, Work wk) {
   __shared__ u32 tmp[SCAN_T];
   const int64_t gb = blockIdx.x;
   const ImgDesc& d = src.by_block(gb);
+  if (!src.ok(d)) return;
   const int64_t n = (int64_t)d.h * d.ntx;
   const int64_t b0 = (gb - d.blk0) * SCAN_B;
   u32 v = 0;
@@ -1503,6 +1519,7 @@ __global__ void __launch_bounds__(SCAN_T) k_scan_apply(Src src, Work wk) {
   __shared__ u32 tmp[SCAN_T];
   const int64_t gb = blockIdx.x;
   const ImgDesc& d = src.by_block(gb);
+  if (!src.ok(d)) return;
   const int64_t n = (int64_t)d.h * d.ntx;
   const int64_t b0 = (gb - d.blk0) * SCAN_B;
   u32 v[4];
@@ -1537,6 +1554,7 @@ template <class T, class Src>
 __global__ void __launch_bounds__(64) k_emit_border(Src src, Work wk) {
   const int64_t gt = blockIdx.x;
   const ImgDesc& d = src.by_tile(gt);
+  if (!src.ok(d)) return;
   const int64_t lt = gt - d.tile0;
   const int tx = (int)(lt % d.ntx), ty = (int)(lt / d.ntx);
   const int y0 = ty * T::TH;
@@ -1569,8 +1587,8 @@ __global__ void __launch_bounds__(256) k_node_canon(Src src, Work wk, int64_t sl
   if (i >= slots) return;
   const int64_t gt = i / T::BCAP;
   const int k = (int)(i % T::BCAP);
-  if (k >= wk.nbt[gt]) return;
   const ImgDesc& d = src.by_tile(gt);
+  if (!src.ok(d) || k >= wk.nbt[gt]) return;
   const int node = (int)(tile_node_base<T>(d, gt - d.tile0) + k);
   wk.ncanon[node] = wk.rcanon[wk.gpar[node]];
 }
@@ -1646,6 +1664,7 @@ __global__ void __launch_bounds__(T::NT) k_tile_emit(Src src, Work wk) {
   __shared__ Acc iacc[T::CAPI];
   const int64_t gt = blockIdx.x;
   const ImgDesc& d = src.by_tile(gt);
+  if (!src.ok(d)) return;
   const int64_t lt = gt - d.tile0;
   const int tx = (int)(lt % d.ntx), ty = (int)(lt / d.ntx);
   const int x0 = tx * T::TW, y0 = ty * T::TH;

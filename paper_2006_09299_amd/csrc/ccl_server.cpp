@@ -210,6 +210,26 @@ struct ccl_server {
     return CCL_OK;
   }
 
+  // a micro-batch that cannot be launched: each of its requests is reported
+  // with the error (its blocks go back to the pool), and so is the lane's
+  // scratch when it was taken
+  void abort_batch(Lane& L, int rc, bool scratch) {
+    if (scratch) {
+      pool.release(L.ws_off, L.ws_len);
+      pool.release(L.desc_off, L.desc_len);
+      pool.release(L.cnt_off, L.cnt_len);
+    }
+    for (int64_t tag : L.tags) {
+      Req& r = reqs[tag];
+      drop_blocks(r);
+      r.status = rc;
+      r.st = DONE;
+      ready.push_back(tag);
+      completed++;
+    }
+    L.tags.clear();
+  }
+
   // admit queue heads into one micro-batch and launch it on lane L
   int launch(Lane& L) {
     std::vector<int64_t>& batch = L.tags;
@@ -229,7 +249,10 @@ struct ccl_server {
       // sizes do not depend on them, but the argument check wants them set
       for (size_t i = 0; i < n; i++) L.imgs[i] = image_of(reqs[batch[i]], reinterpret_cast<int64_t*>(base));
       int rc = ccl_batch_sizes(L.imgs.data(), (int32_t)n, cfg.variant, &db, &wb);
-      if (rc != CCL_OK && !(rc == CCL_ETOOBIG && n > 1)) return rc;
+      if (rc != CCL_OK && !(rc == CCL_ETOOBIG && n > 1)) {
+        abort_batch(L, rc, false);
+        return CCL_OK;
+      }
       if (rc == CCL_OK) {
         L.ws_off = pool.alloc(wb);
         L.desc_off = L.ws_off == ccl::Pool::NONE ? ccl::Pool::NONE : pool.alloc(db);
@@ -255,7 +278,10 @@ struct ccl_server {
     for (size_t i = 0; i < n; i++) L.imgs[i].out.counts = cnt + 2 * i;
     if (!L.desc.ensure(db) || !L.counts.ensure(L.cnt_len)) return fail(hipErrorOutOfMemory);
     int rc = ccl_batch_prepare(L.imgs.data(), (int32_t)n, cfg.variant, L.desc.p, db);
-    if (rc != CCL_OK) return rc;
+    if (rc != CCL_OK) {
+      abort_batch(L, rc, true);
+      return CCL_OK;
+    }
     for (size_t i = 0; i < n; i++) {
       Req& r = reqs[batch[i]];
       hipError_t e = r.pitch == r.w
@@ -270,7 +296,14 @@ struct ccl_server {
     if (e != hipSuccess) return fail(e);
     rc = ccl_label_batch(L.imgs.data(), (int32_t)n, cfg.variant, base + L.desc_off, base + L.ws_off, wb, L.stream);
     if (rc == CCL_EHIP) return fail(hipErrorLaunchFailure);
-    if (rc != CCL_OK) return rc;
+    if (rc != CCL_OK) {
+      // the uploads are already enqueued: the host images stay in use until
+      // they are done
+      e = hipStreamSynchronize(L.stream);
+      if (e != hipSuccess) return fail(e);
+      abort_batch(L, rc, true);
+      return CCL_OK;
+    }
     e = hipMemcpyAsync(L.counts.p, cnt, L.cnt_len, hipMemcpyDeviceToHost, L.stream);
     if (e == hipSuccess) e = hipEventRecord(L.finished, L.stream);
     if (e != hipSuccess) return fail(e);

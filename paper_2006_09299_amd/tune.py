@@ -42,16 +42,28 @@ def _store(path: str, data: Dict[str, dict]) -> None:
     os.replace(tmp, path)
 
 
+def variants_digest() -> str:
+    """Digest of the variant table of the loaded library (shape, reduction,
+    workgroup size, merge schedule of every index): a cache entry written for
+    another table is never used."""
+    import hashlib
+    h = hashlib.sha256()
+    for v in range(_capi.num_variants()):
+        h.update(repr(tuple(_capi.variant_info(v))).encode())
+    return h.hexdigest()[:12]
+
+
 def workload_key(imgs: Sequence[torch.Tensor]) -> str:
-    """arch / log2(mean pixels per image) / run-density bucket (horizontal
-    colour changes per pixel, in steps of 0.05)."""
+    """arch / variant table digest / log2(mean pixels per image) /
+    run-density bucket (horizontal colour changes per pixel, in steps of
+    0.05)."""
     arch = torch.cuda.get_device_properties(imgs[0].device).gcnArchName.split(":")[0]
     px = sum(int(t.numel()) for t in imgs) / len(imgs)
     sample = imgs[: min(len(imgs), 16)]
     changes = sum(int((t[:, 1:] != t[:, :-1]).sum()) for t in sample)
     total = sum(int(t.numel()) for t in sample)
     dens = changes / max(total, 1)
-    return f"{arch}/px2^{round(math.log2(max(px, 1)))}/runs{round(dens / 0.05) * 0.05:.2f}"
+    return f"{arch}/v{variants_digest()}/px2^{round(math.log2(max(px, 1)))}/runs{round(dens / 0.05) * 0.05:.2f}"
 
 
 def time_variant(imgs: Sequence[torch.Tensor], variant: int, reps: int = 3) -> float:
@@ -77,7 +89,12 @@ def autotune(imgs: Sequence[torch.Tensor], variants: Optional[Sequence[int]] = N
     key = workload_key(imgs)
     data = _load(path)
     if not force and key in data:
-        return int(data[key]["variant"])
+        try:
+            v = int(data[key]["variant"])
+        except (KeyError, TypeError, ValueError):
+            v = -1
+        if 0 <= v < _capi.num_variants():
+            return v  # else: a damaged entry, timed again
     if variants is None:
         variants = range(_capi.num_variants())
     timings = {int(v): time_variant(imgs, int(v), reps) for v in variants}

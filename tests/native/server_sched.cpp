@@ -10,6 +10,9 @@
 //     n_labels entries, or is reported CCL_ENOSPC when that can never fit;
 //   - with one stream and no relaunch, requests finish in submission order;
 //   - batches with too many union-find nodes are split;
+//   - a micro-batch that a batch entry point refuses (size query, descriptor
+//     preparation or launch) reports each of its requests with that error,
+//     frees their blocks and the lane's scratch, and the server goes on;
 //   - after the last release the pool is empty, and destroy frees every
 //     stream, event and pinned buffer.
 // Prints "ok" and exits 0, or prints the failed check and exits 1.
@@ -51,6 +54,18 @@ static int64_t g_label_range;  // true label count of an image: 1 + checksum % m
 static int64_t g_launches_seen;
 // path coverage over all scenarios
 static int64_t n_sizes_calls, n_toobig, n_launch_total, n_relaunched, n_refused, n_enospc_done;
+// refused micro-batches: an image of one of these shapes makes the stand-in
+// of that entry point return CCL_EINVAL (only in scenarios that plant them)
+static bool g_poison;
+enum { POISON_NONE, POISON_SIZES, POISON_PREPARE, POISON_LAUNCH };
+static int poison_of(int32_t w, int32_t h) {
+  if (!g_poison) return POISON_NONE;
+  if (w == 23 && h == 11) return POISON_SIZES;
+  if (w == 17 && h == 19) return POISON_PREPARE;
+  if (w == 19 && h == 17) return POISON_LAUNCH;
+  return POISON_NONE;
+}
+static int64_t n_poison_sizes, n_poison_prepare, n_poison_launch, n_failed_reports;
 
 static uint32_t checksum(const uint8_t* p, int32_t w, int32_t h, int64_t pitch) {
   uint32_t s = 2166136261u;
@@ -73,6 +88,10 @@ int ccl_batch_sizes(const ccl_image_t* imgs, int32_t n, int32_t variant, size_t*
   size_t ws = 0;
   for (int i = 0; i < n; i++) {
     CHECK(imgs[i].img && imgs[i].out.counts && imgs[i].pitch == imgs[i].w);
+    if (poison_of(imgs[i].w, imgs[i].h) == POISON_SIZES) {
+      n_poison_sizes++;
+      return CCL_EINVAL;
+    }
     px += (int64_t)imgs[i].w * imgs[i].h;
     ws += ccl_workspace_bytes_v(imgs[i].w, imgs[i].h, variant);
   }
@@ -86,12 +105,22 @@ int ccl_batch_sizes(const ccl_image_t* imgs, int32_t n, int32_t variant, size_t*
 }
 int ccl_batch_prepare(const ccl_image_t* imgs, int32_t n, int32_t, void* host_desc, size_t db) {
   CHECK(db >= 144 * (size_t)n);
+  for (int i = 0; i < n; i++)
+    if (poison_of(imgs[i].w, imgs[i].h) == POISON_PREPARE) {
+      n_poison_prepare++;
+      return CCL_EINVAL;
+    }
   for (int i = 0; i < n; i++) memcpy(static_cast<char*>(host_desc) + 144 * i, &imgs[i], sizeof(void*));
   return CCL_OK;
 }
 int ccl_label_batch(const ccl_image_t* imgs, int32_t n, int32_t, const void* dev_desc, void* ws, size_t wb,
                     void* stream) {
   CHECK(n >= 1 && n <= g_max_batch && stream);
+  for (int i = 0; i < n; i++)
+    if (poison_of(imgs[i].w, imgs[i].h) == POISON_LAUNCH) {
+      n_poison_launch++;
+      return CCL_EINVAL;
+    }
   g_launches_seen++;
   n_launch_total++;
   for (int i = 0; i < n; i++) CHECK(memcmp(static_cast<const char*>(dev_desc) + 144 * i, &imgs[i], sizeof(void*)) == 0);
@@ -153,10 +182,17 @@ static void scenario(int s) {
   g_px_limit = 100000 + rnd(100000);
   mock_event_latency = rnd(3) ? latency_small : latency_none;
   int nreq = 30 + rnd(30);
+  g_poison = rnd(3) == 0;
   std::vector<HostReq> reqs(nreq);
   for (auto& r : reqs) {
     r.w = 1 + rnd(rnd(2) ? 300 : 40);
     r.h = 1 + rnd(rnd(2) ? 300 : 40);
+    if (g_poison && rnd(8) == 0) {
+      static const int shapes[3][2] = {{23, 11}, {17, 19}, {19, 17}};
+      const int k = rnd(3);
+      r.w = shapes[k][0];
+      r.h = shapes[k][1];
+    }
     r.pitch = r.w + rnd(9);
     r.img.resize((size_t)r.pitch * r.h);
     for (auto& b : r.img) b = (uint8_t)rnd(256);
@@ -206,6 +242,12 @@ static void scenario(int s) {
       reported++;
       order.push_back((int)d.tag);
       CHECK(d.w == r.w && d.h == r.h && d.out.counts == nullptr);
+      if (poison_of(r.w, r.h) != POISON_NONE) CHECK(d.status == CCL_EINVAL);
+      if (d.status == CCL_EINVAL) {  // its micro-batch was refused
+        CHECK(g_poison && d.out.labels == nullptr && d.launches <= 2);
+        n_failed_reports++;
+        continue;
+      }
       int64_t nl = true_labels(r.cs, r.w, r.h);
       CHECK(d.n_labels == nl && d.euler == (int64_t)(r.cs % 1000) - 500);
       int64_t cap1 = std::min<int64_t>((int64_t)r.w * r.h + 1, std::max<int64_t>(1024, ((int64_t)r.w * r.h + 1) / cfg.cap_divisor));
@@ -239,11 +281,12 @@ static void scenario(int s) {
       if (all) {
         CHECK(st.queued == 0 && st.in_flight == 0 && st.live == 0 && st.pool_used == 0 && st.ready == 0);
         CHECK(st.completed == accepted && st.launches == g_launches_seen);
+        CHECK(st.in_flight == 0);
         break;
       }
     }
   }
-  if (cfg.streams == 1 && !relaunch) CHECK(std::is_sorted(order.begin(), order.end()));
+  if (cfg.streams == 1 && !relaunch && !g_poison) CHECK(std::is_sorted(order.begin(), order.end()));
   CHECK(ccl_server_destroy(srv) == CCL_OK);
   CHECK(mock_live_streams == 0 && mock_live_events == 0 && mock_live_pinned == 0);
 }
@@ -256,8 +299,10 @@ int main(int argc, char** argv) {
   }
   // retries: size queries that did not end in a launch (too many nodes, or
   // scratch that did not fit and made the micro-batch shrink)
-  printf("ok %d scenarios: launches %lld retries %lld toobig %lld relaunched %lld refused %lld enospc_done %lld\n", n,
+  printf("ok %d scenarios: launches %lld retries %lld toobig %lld relaunched %lld refused %lld enospc_done %lld "
+         "failed_sizes %lld failed_prepare %lld failed_launch %lld failed_reports %lld\n", n,
          (long long)n_launch_total, (long long)(n_sizes_calls - n_launch_total), (long long)n_toobig,
-         (long long)n_relaunched, (long long)n_refused, (long long)n_enospc_done);
+         (long long)n_relaunched, (long long)n_refused, (long long)n_enospc_done, (long long)n_poison_sizes,
+         (long long)n_poison_prepare, (long long)n_poison_launch, (long long)n_failed_reports);
   return 0;
 }

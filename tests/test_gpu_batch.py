@@ -130,3 +130,36 @@ def test_autotune_picks_and_caches(tmp_path):
     rs = ccl.label_batch(imgs, variant=v)
     torch.cuda.synchronize()
     _same(rs[0], oracle.label(imgs[0].cpu().numpy()))
+
+
+def test_full_uneven_batch_4096(tmp_path):
+    """The benchmarked uneven batch at its full size: 4096 images with sides
+    log-uniform in [64, 2048], the variant the autotuner picks on the same
+    sample the benchmark tunes on, captured into a HIP graph and replayed
+    twice; every image against the oracle, element by element."""
+    import concurrent.futures as cf
+    import os
+    import paper_2006_09299_amd as ccl
+    from paper_2006_09299_amd import tune
+    dev = _dev()
+    specs = synth.batch_specs(4096)
+    host = [sp.make() for sp in specs]
+    imgs = [torch.from_numpy(im).to(dev) for im in host]
+    _say("batch 4096:", sum(sp.pixels for sp in specs), "pixels")
+    v = tune.autotune(imgs[::16], path=str(tmp_path / "tune.json"))
+    _say("batch 4096: autotuned variant", v, ccl.variant_info(v))
+    first = ccl.label_batch(imgs, variant=v)  # table capacities
+    caps = [r.n_labels + 16 for r in first]
+    del first
+    plan = ccl.BatchPlan(imgs, variant=v, caps=caps)
+    plan.capture()
+    for _ in range(2):
+        plan.replay()
+    torch.cuda.synchronize()
+    rs = plan.results()
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with cf.ThreadPoolExecutor(workers) as ex:  # the oracle's C call releases the GIL
+        for k, o in enumerate(ex.map(oracle.label, host)):
+            if k % 512 == 0:
+                _say("batch 4096: image", k, host[k].shape)
+            _same(rs[k], o)

@@ -144,7 +144,8 @@ def test_server_scheduling_on_a_mock_runtime(tmp_path):
     batch entry points; 300 random configurations (see the driver's header
     for the checks).  Every path must be taken at least once: shrinking
     micro-batches, relaunch with the exact capacity, refusal at submit and
-    at relaunch."""
+    at relaunch, and micro-batches that a batch entry point refuses (each
+    request reported with the error, its memory returned)."""
     exe = str(tmp_path / "server_sched")
     subprocess.run(["g++", "-std=c++17", "-O1", "-Wall", "-Werror", "-fsanitize=address,undefined",
                     "-I", os.path.join(HERE, "native", "mock"), os.path.join(HERE, "native", "server_sched.cpp"),
@@ -154,5 +155,6 @@ def test_server_scheduling_on_a_mock_runtime(tmp_path):
     words = p.stdout.split()
     assert words[0] == "ok"
     stats = {k: int(v) for k, v in zip(words[3::2], words[4::2])}
-    for k in ("launches", "retries", "toobig", "relaunched", "refused", "enospc_done"):
+    for k in ("launches", "retries", "toobig", "relaunched", "refused", "enospc_done", "failed_sizes",
+              "failed_prepare", "failed_launch", "failed_reports"):
         assert stats[k] > 0, (k, p.stdout)
