@@ -630,6 +630,45 @@ def oracle_timings(sweep, batch_host):
     return out
 
 
+# The paper's CPU timings (Sec. 4: 2048 x 2048 random images by density and
+# granularity, one thread of a Skylake Gold 6126 @ 2.60 GHz), cycles per pixel
+PAPER_TABLE1_CPP = {"BWA": [2.80, 15.3], "+Euler": [0.0, 0.66], "+hole filling": [0.0, 0.74],
+                    "+features": [0.0, 10.3], "+relabeling": [0.59, 13.2]}
+PAPER_TABLE2_CPP = {"BWAR": [3.41, 28.9], "BWAER": [3.41, 29.0], "BWAE": [2.80, 15.9], "BWAF": [2.80, 24.8]}
+
+
+def host_lsl_bw(side: int = 2048, reps: int = 5):
+    """The paper's own algorithm on the host (liblslbw.so, one thread), in
+    cycles per pixel on side x side Bernoulli images of the sweep's densities
+    and granularities, per configuration of Tables 1 and 2; the best of `reps`
+    calls per image, then min / max over the images (the paper's protocol).
+    Cycles are time-stamp-counter ticks, i.e. at the host's nominal clock."""
+    import synth
+    from paper_2006_09299_amd import lslbw
+    ctx = lslbw.Context(side, side)
+    per = {name: [] for name in lslbw.CONFIGS}
+    t0 = time.perf_counter()
+    for gi, g in enumerate(synth.SWEEP_G):
+        for pi, p in enumerate(synth.SWEEP_P):
+            img = synth.bernoulli_blocks(side, side, p, g, 100 + 5 * gi + pi)
+            for name, fl in lslbw.CONFIGS.items():
+                per[name].append(min(ctx.label(img, fl).tsc for _ in range(reps)) / img.size)
+    ctx.close()
+    cpp = {k: [round(min(v), 2), round(max(v), 2)] for k, v in per.items()}
+    extra = {"+Euler": "BWAE", "+hole filling": "BWA+fill", "+features": "BWAF", "+relabeling": "BWAR"}
+    table1 = {"BWA": cpp["BWA"]}
+    for k, cfg in extra.items():  # extra time over the base, image by image
+        d = [a - b for a, b in zip(per[cfg], per["BWA"])]
+        table1[k] = [round(min(d), 2), round(max(d), 2)]
+    say(f"  host LSL-BW: {time.perf_counter() - t0:.1f} s")
+    return {"images": f"{side}x{side}, p in {list(synth.SWEEP_P)} x g in {list(synth.SWEEP_G)}",
+            "unit": "cycles/pixel (min, max over images)", "threads": 1, "host": host_cpu(),
+            "table1": {"ours": table1, "paper": PAPER_TABLE1_CPP},
+            "table2": {"ours": {k: cpp[k] for k in PAPER_TABLE2_CPP}, "paper": PAPER_TABLE2_CPP},
+            "all_configs": cpp,
+            "paper_host": "Skylake Gold 6126 @ 2.60 GHz, one thread"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -734,6 +773,9 @@ def main():
         if sweep is not None:
             say("bench: oracle on 512^2, the sweep and the batch")
             also["oracle"] = oracle_timings(sweep, batch_host)
+        say("bench: the paper's algorithm on the host (single-thread LSL-BW), cycles per pixel")
+        also["host_lsl_bw"] = host_lsl_bw()
+        say(f"  {json.dumps(also['host_lsl_bw'])}")
     if also:
         out["also"] = also
     print(json.dumps(out), flush=True)

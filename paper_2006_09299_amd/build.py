@@ -1,4 +1,5 @@
-"""Compile libccl.so (HIP, gfx950) in-tree with hipcc."""
+"""Compile libccl.so (HIP, gfx950) in-tree with hipcc, and the host LSL-BW
+(liblslbw.so) with g++."""
 from __future__ import annotations
 
 import os
@@ -19,7 +20,20 @@ FLAGS = [
 ]
 
 
+HOST_SRC = os.path.join(HERE, "host", "lsl_bw.cpp")
+HOST_LIB = os.path.join(HERE, "host", "liblslbw.so")
+
+
+def build_host() -> str:
+    """liblslbw.so: the single-thread host LSL-BW (plain g++, no GPU code)."""
+    tmp = HOST_LIB + ".tmp"
+    subprocess.check_call(["g++", "-O3", "-std=c++17", "-fPIC", "-shared", "-Wall", "-Wextra", HOST_SRC, "-o", tmp])
+    os.replace(tmp, HOST_LIB)
+    return HOST_LIB
+
+
 def build() -> str:
+    build_host()
     srcs = [os.path.join(CSRC, f) for f in SOURCES]
     tmp = LIB + ".tmp"
     cmd = [HIPCC, *FLAGS, *srcs, "-o", tmp]
