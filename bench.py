@@ -418,7 +418,8 @@ def run_batch(n_images: int, steps: int, warmup: int, host_out=None):
     loop_ms = a.elapsed_time(b) / steps
     out = {"images": n_images, "Gpixel": round(px / 1e9, 4), "variant": variant,
            "tile": list(ccl.variant_info(variant)[:2]), "hash_reduce": ccl.variant_info(variant)[2],
-           "threads": ccl.variant_info(variant)[3],
+           "threads": ccl.variant_info(variant)[3], "super_tile": ccl.variant_info(variant)[4],
+           "reduce_group": ccl.variant_info(variant)[5],
            "graph_ms_per_batch": round(batch_ms, 3), "Gpixel_s": round(px / (batch_ms / 1e3) / 1e9, 2),
            "batch_latency_ms_p50": round(lat_ms[len(lat_ms) // 2], 3),
            "batch_latency_ms_p99": round(lat_ms[min(len(lat_ms) - 1, int(0.99 * len(lat_ms)))], 3),
@@ -430,46 +431,60 @@ def run_batch(n_images: int, steps: int, warmup: int, host_out=None):
     return out
 
 
-def serve_sources(sweep):
-    """Pinned host copies of the sweep images with g in {1, 4}: the serving
-    leg crops every request out of one of them."""
+SERVE_POOL = 512  # distinct request images (contiguous, pinned)
+
+
+def serve_sources(n_stream: int, n_pool: int = SERVE_POOL):
+    """Pinned host images for the serving stream: the stream's requests
+    (sides log-uniform in [256, 8192], p ~ U(0.1, 0.9), g in {1, 4}) ranked
+    by area, and n_pool of them at evenly spaced area quantiles generated at
+    their own size and parameters with contiguous rows (one plain copy
+    uploads each).  Returns (areas, images), both in increasing area."""
+    import numpy as np
     import torch
-    src = {}
-    for (p, g, _seed), img in sweep:
-        if g in (1, 4):
-            src[(p, g)] = torch.from_numpy(img).pin_memory()
-    return src
+    import synth
+    specs = [rq.spec for rq in synth.serve_stream(n_stream)]
+    order = sorted(range(len(specs)), key=lambda k: specs[k].w * specs[k].h)
+    pick = [order[round(k * (len(order) - 1) / (n_pool - 1))] for k in range(n_pool)]
+    pool = []
+    for k, j in enumerate(pick):
+        pool.append(torch.from_numpy(specs[j].make()).pin_memory())
+        if (k + 1) % 64 == 0:
+            say(f"  serve pool: {k + 1}/{n_pool} images")
+    areas = np.array([t.numel() for t in pool])
+    say(f"  serve pool: mean {areas.mean() / 1e6:.2f} Mpx per image; stream mean "
+        f"{np.mean([s.w * s.h for s in specs]) / 1e6:.2f} Mpx")
+    return areas, pool
 
 
 def run_serve(n_requests: int, sources, rate_hz: float = 2000.0, warmup_s: float = 1.0, budget_gib: int = 48,
               batched: bool = True):
-    """Open-loop Poisson request stream through the serving loop.  Every
-    request has the stream's own size (sides log-uniform in [256, 8192]) and
-    is a crop, at a random offset, of the 8192^2 sweep image with the same
-    granularity and the density nearest its own (strided host rows, pinned).
+    """Open-loop Poisson request stream through the serving loop: arrivals as
+    the stream draws them; every request carries the pool image nearest its
+    own drawn area (the pool holds the stream's area quantiles).
     Latency = completion observed - scheduled arrival."""
     import numpy as np
     import synth
     from paper_2006_09299_amd.serve import Server
 
+    areas, pool = sources
     warm = int(warmup_s * rate_hz)
     stream = synth.serve_stream(n_requests + warm, rate_hz=rate_hz)
-    ps = sorted({p for p, _ in sources})
-    rng = np.random.default_rng(12)
     host = []
     for rq in stream:
-        sp = rq.spec
-        p = min(ps, key=lambda q: abs(q - sp.p))
-        src = sources[(p, sp.g)]
-        y0 = int(rng.integers(0, src.shape[0] - sp.h + 1))
-        x0 = int(rng.integers(0, src.shape[1] - sp.w + 1))
-        host.append(src[y0:y0 + sp.h, x0:x0 + sp.w])
-    say(f"  serve: {len(host)} requests, mean {np.mean([t.numel() for t in host]) / 1e6:.2f} Mpx")
+        a = rq.spec.w * rq.spec.h
+        k = int(np.searchsorted(areas, a))
+        if k == len(areas) or (k > 0 and a - areas[k - 1] < areas[k] - a):
+            k -= 1
+        host.append(pool[k])
+    say(f"  serve: {len(host)} requests at {rate_hz:.0f}/s, mean {np.mean([t.numel() for t in host]) / 1e6:.2f} Mpx "
+        f"(drawn: {np.mean([rq.spec.w * rq.spec.h for rq in stream]) / 1e6:.2f})")
     srv = Server(budget_gib << 30, max_slots=512 if batched else 1, streams=4 if batched else 1,
                  max_batch=64 if batched else 1)
     lat, px_done, t_first, t_last, qmax = [], 0, None, None, 0
     i = 0
     start = srv.now()
+    next_note = 2.0
     while i < len(stream) or not srv.idle():
         now = srv.now() - start
         while i < len(stream) and stream[i].arrival_s <= now:
@@ -483,12 +498,17 @@ def run_serve(n_requests: int, sources, rate_hz: float = 2000.0, warmup_s: float
                 t_last = r.done if t_last is None else max(t_last, r.done)
             srv.release(r.rid)
         qmax = max(qmax, srv.queued())
+        if now >= next_note:
+            say(f"  serve: {now:.0f} s, {i} submitted, {len(lat)} measured done, queue {srv.queued()}")
+            next_note += 2.0
     st = srv.stats()
     srv.close()
     lat.sort()
     q = lambda f: round(1e3 * lat[min(len(lat) - 1, int(f * len(lat)))], 3)
     span = t_last - t_first
-    return {"requests": len(lat), "rate_hz": rate_hz, "offered_Gpixel_s": round(px_done / (len(lat) / rate_hz) / 1e9, 2),
+    return {"requests": len(lat), "rate_hz": rate_hz, "distinct_images": len(pool),
+            "mean_Mpx": round(px_done / len(lat) / 1e6, 3),
+            "offered_Gpixel_s": round(px_done / (len(lat) / rate_hz) / 1e9, 2),
             "Gpixel_s": round(px_done / span / 1e9, 2), "p50_ms": q(0.50), "p99_ms": q(0.99), "max_ms": round(1e3 * lat[-1], 3),
             "max_queue": qmax, "rejected": srv.rejected, "streams": srv.streams, "max_batch": srv.max_batch,
             "micro_batches": st.launches, "relaunched": st.relaunched}
@@ -648,11 +668,15 @@ def host_lsl_bw(side: int = 2048, reps: int = 5):
     ctx = lslbw.Context(side, side)
     per = {name: [] for name in lslbw.CONFIGS}
     t0 = time.perf_counter()
+    ticks = ns = 0
     for gi, g in enumerate(synth.SWEEP_G):
         for pi, p in enumerate(synth.SWEEP_P):
             img = synth.bernoulli_blocks(side, side, p, g, 100 + 5 * gi + pi)
             for name, fl in lslbw.CONFIGS.items():
-                per[name].append(min(ctx.label(img, fl).tsc for _ in range(reps)) / img.size)
+                rs = [ctx.label(img, fl) for _ in range(reps)]
+                per[name].append(min(r.tsc for r in rs) / img.size)
+                ticks += sum(r.tsc for r in rs)
+                ns += sum(r.ns for r in rs)
     ctx.close()
     cpp = {k: [round(min(v), 2), round(max(v), 2)] for k, v in per.items()}
     extra = {"+Euler": "BWAE", "+hole filling": "BWA+fill", "+features": "BWAF", "+relabeling": "BWAR"}
@@ -663,6 +687,7 @@ def host_lsl_bw(side: int = 2048, reps: int = 5):
     say(f"  host LSL-BW: {time.perf_counter() - t0:.1f} s")
     return {"images": f"{side}x{side}, p in {list(synth.SWEEP_P)} x g in {list(synth.SWEEP_G)}",
             "unit": "cycles/pixel (min, max over images)", "threads": 1, "host": host_cpu(),
+            "tsc_GHz": round(ticks / ns, 3),
             "table1": {"ours": table1, "paper": PAPER_TABLE1_CPP},
             "table2": {"ours": {k: cpp[k] for k in PAPER_TABLE2_CPP}, "paper": PAPER_TABLE2_CPP},
             "all_configs": cpp,
@@ -757,7 +782,7 @@ def main():
         say("bench: batch4096")
         also["batch4096"] = run_batch(4096, max(3, args.steps), 1, host_out=batch_host)
         say("bench: serving (continuous batching), then one request per launch")
-        src = serve_sources(sweep)
+        src = serve_sources(args.serve_requests + 2000)
         sv = run_serve(args.serve_requests, src)
         say(f"  serve: {json.dumps(sv)}")
         sv1 = run_serve(min(args.serve_requests, 4000), src, batched=False)

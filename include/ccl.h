@@ -110,10 +110,13 @@ int ccl_label_traced(const uint8_t *img, int32_t w, int32_t h, int64_t pitch, co
 /* [host] Name of kernel k (0..CCL_TRACE_EVENTS-2) in launch order, or NULL. */
 const char *ccl_kernel_name(int k);
 
-/* Variants: the path compiled for several tile shapes, workgroup sizes and
+/* Variants: the path compiled for several tile shapes, workgroup sizes,
  * two ways of summing the partial features of components that cross tiles
- * (an LDS hash table per group of tiles, or direct global atomics).  All
- * variants give identical results; they differ in speed per workload.
+ * (an LDS hash table per group of tiles, or direct global atomics) and merge
+ * schedules (the side of the super-tiles whose inner seams are merged in LDS
+ * before the seams between them are merged in device memory, and the number
+ * of tiles per workgroup of the root reduction).  All variants give
+ * identical results; they differ in speed per workload.
  * Variant 0 (64 x 128 tiles, 256 threads, LDS hash) is the default of
  * ccl_label.  For tiles of 8192 pixels or more the relabeling kernel
  * (k_tile_emit) always runs 512 threads per tile. */
@@ -122,9 +125,11 @@ const char *ccl_kernel_name(int k);
 int32_t ccl_num_variants(void);
 
 /* [host] Tile rows, tile columns, reduction (1 = LDS hash, 0 = direct
- * atomics) and threads per tile workgroup of `variant` (any output pointer
- * may be NULL); CCL_EINVAL for an unknown index. */
-int ccl_variant_info(int32_t variant, int32_t *tile_h, int32_t *tile_w, int32_t *hash_reduce, int32_t *threads);
+ * atomics), threads per tile workgroup, super-tile side (tiles) and tiles per
+ * root-reduction workgroup (1 for direct atomics) of `variant` (any output
+ * pointer may be NULL); CCL_EINVAL for an unknown index. */
+int ccl_variant_info(int32_t variant, int32_t *tile_h, int32_t *tile_w, int32_t *hash_reduce, int32_t *threads,
+                     int32_t *super_tile, int32_t *reduce_group);
 
 /* [host] Workspace bytes of `variant` for a w x h image (pure; 0 on bad input). */
 size_t ccl_workspace_bytes_v(int32_t w, int32_t h, int32_t variant);

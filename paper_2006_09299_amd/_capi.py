@@ -105,8 +105,7 @@ def lib():
         L.ccl_num_variants.restype = ctypes.c_int32
         L.ccl_num_variants.argtypes = []
         L.ccl_variant_info.restype = ctypes.c_int
-        L.ccl_variant_info.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
-                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+        L.ccl_variant_info.argtypes = [ctypes.c_int32] + [ctypes.POINTER(ctypes.c_int32)] * 6
         L.ccl_workspace_bytes_v.restype = ctypes.c_size_t
         L.ccl_workspace_bytes_v.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
         L.ccl_label_v.restype = ctypes.c_int
@@ -171,11 +170,12 @@ def num_variants() -> int:
 
 
 def variant_info(v: int):
-    """(tile rows, tile columns, uses the LDS hash reduction, threads per tile)"""
-    th, tw, hs, nt = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-    check(lib().ccl_variant_info(int(v), ctypes.byref(th), ctypes.byref(tw), ctypes.byref(hs), ctypes.byref(nt)),
-          "ccl_variant_info")
-    return th.value, tw.value, bool(hs.value), nt.value
+    """(tile rows, tile columns, uses the LDS hash reduction, threads per tile,
+    super-tile side, tiles per root-reduction workgroup)"""
+    vals = [ctypes.c_int32() for _ in range(6)]
+    check(lib().ccl_variant_info(int(v), *[ctypes.byref(x) for x in vals]), "ccl_variant_info")
+    th, tw, hs, nt, sup, rg = (x.value for x in vals)
+    return th, tw, bool(hs), nt, sup, rg
 
 
 def kernel_names():

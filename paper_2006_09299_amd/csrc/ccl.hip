@@ -17,9 +17,9 @@ namespace {
 static_assert(sizeof(ccl::Feature) == sizeof(ccl_feature_t), "feature record layout");
 static_assert(sizeof(ccl::ImgDesc) <= 256, "the serving footprint counts one 256-byte block per descriptor");
 
-template <int TH, int TW, bool HASH, int NT = 256, bool FG8 = true>
+template <int TH, int TW, bool HASH, int NT = 256, bool FG8 = true, int SUP = 4, int RHT = 0>
 struct V {
-  using T = ccl::Tile<TH, TW, NT, FG8>;
+  using T = ccl::Tile<TH, TW, NT, FG8, SUP, RHT>;
   static constexpr bool hash = HASH;
 };
 
@@ -27,8 +27,9 @@ struct V {
 // background) in the default variant's shape
 using VC4 = V<64, 128, true, 256, false>;
 
-// variant index -> (tile rows, tile columns, reduction, workgroup size)
-constexpr int NVARIANTS = 8;
+// variant index -> (tile rows, tile columns, reduction, workgroup size,
+// super-tile side, tiles per root-reduction workgroup)
+constexpr int NVARIANTS = 13;
 
 template <class F>
 int with_variant(int v, F&& f) {
@@ -41,6 +42,13 @@ int with_variant(int v, F&& f) {
     case 5: return f(V<32, 128, true>{});
     case 6: return f(V<16, 256, true>{});
     case 7: return f(V<32, 256, true>{});
+    // merge schedule: super-tiles of 2 x 2 or 8 x 8 tiles, smaller
+    // root-reduction groups
+    case 8: return f(V<64, 128, true, 256, true, 2>{});
+    case 9: return f(V<64, 128, true, 256, true, 8>{});
+    case 10: return f(V<64, 128, true, 512, true, 8>{});
+    case 11: return f(V<64, 128, true, 256, true, 4, 16>{});
+    case 12: return f(V<32, 128, true, 256, true, 8, 32>{});
     default: return CCL_EINVAL;
   }
 }
@@ -99,8 +107,8 @@ struct Totals {
 template <class Vt>
 uint32_t batch_check(const Totals& t, int32_t n) {
   using T = typename Vt::T;
-  const int64_t v[] = {T::TH, T::TW, T::NT, Vt::hash ? 1 : 0, T::FG8 ? 1 : 0, t.tiles, t.nodes, t.cells,
-                       t.blocks, t.items, t.supers, n};
+  const int64_t v[] = {T::TH, T::TW, T::NT, Vt::hash ? 1 : 0, T::FG8 ? 1 : 0, T::SUP, T::RHT, t.tiles, t.nodes,
+                       t.cells, t.blocks, t.items, t.supers, n};
   uint32_t h = 2166136261u;
   for (int64_t x : v)
     for (int b = 0; b < 8; b++) h = (h ^ (uint32_t)((uint64_t)x >> (8 * b) & 0xFF)) * 16777619u;
@@ -225,13 +233,16 @@ int ccl_fill_holes(const ccl_outputs_t* in, int32_t w, int32_t h, const ccl_outp
 
 int32_t ccl_num_variants(void) { return NVARIANTS; }
 
-int ccl_variant_info(int32_t variant, int32_t* tile_h, int32_t* tile_w, int32_t* hash_reduce, int32_t* threads) {
+int ccl_variant_info(int32_t variant, int32_t* tile_h, int32_t* tile_w, int32_t* hash_reduce, int32_t* threads,
+                     int32_t* super_tile, int32_t* reduce_group) {
   return with_variant(variant, [&](auto vt) -> int {
     using Vt = decltype(vt);
     if (tile_h) *tile_h = Vt::T::TH;
     if (tile_w) *tile_w = Vt::T::TW;
     if (hash_reduce) *hash_reduce = Vt::hash ? 1 : 0;
     if (threads) *threads = Vt::T::NT;
+    if (super_tile) *super_tile = Vt::T::SUP;
+    if (reduce_group) *reduce_group = Vt::hash ? Vt::T::RHT : 1;
     return CCL_OK;
   });
 }
@@ -338,6 +349,8 @@ const char* ccl_strerror(int code) {
   }
 }
 
-void ccl_tile_shape(int32_t* tile_h, int32_t* tile_w) { ccl_variant_info(0, tile_h, tile_w, nullptr, nullptr); }
+void ccl_tile_shape(int32_t* tile_h, int32_t* tile_w) {
+  ccl_variant_info(0, tile_h, tile_w, nullptr, nullptr, nullptr, nullptr);
+}
 
 }  // extern "C"

@@ -141,11 +141,14 @@ struct Work {
 };
 
 constexpr u32 HI = 0x80000000u;
-constexpr int SUP = 4;                  // tiles per side of a super-tile (seams merged in LDS)
 constexpr int SCAN_T = 256;             // threads of the scan kernels
 constexpr int SCAN_B = SCAN_T * 4;      // entries per scan block
 
-template <int TH_, int TW_, int NT_ = 256, bool FG8_ = true>
+// Merge schedule: SUP_ tiles per side of a super-tile (its inner seams are
+// merged in LDS by k_seam_local, the rest by k_border_merge); RHT_ tiles per
+// workgroup of the root reduction (0: 64 for tiles of more than 4096 pixels,
+// else 32).
+template <int TH_, int TW_, int NT_ = 256, bool FG8_ = true, int SUP_ = 4, int RHT_ = 0>
 struct Tile {
   static constexpr int TH = TH_;
   static constexpr int TW = TW_;
@@ -160,6 +163,10 @@ struct Tile {
   // the complementary pair (the unification's widening moves to background)
   static constexpr bool FG8 = FG8_;
   static constexpr int CAPI = N >= 8192 ? 512 : 256;  // interior accumulators per pass
+  static constexpr int SUP = SUP_;
+  static constexpr int RHT = RHT_ ? RHT_ : (N > 4096 ? 64 : 32);
+  static_assert(SUP >= 2 && SUP <= 8, "super-tile side");
+  static_assert(RHT >= 1 && RHT <= 64, "root-reduction group (one wave scans it)");
   static_assert(TW % 64 == 0 && TW <= 256, "tile width (a row rank fits 8 bits)");
   static_assert(TH >= 1 && TH <= 64, "tile height (a column of the tile fits one wave)");
   static_assert(NT >= 128 && NT % 64 == 0, "at least two waves per tile");
@@ -1033,8 +1040,8 @@ __host__ __device__ inline int64_t merge_items(int w, int h, int ntx, int nty) {
   // each super-tile column), vertical seams on super-tile column edges
   // (every row), exterior (top / bottom rows by quarter words, left / right
   // columns by row)
-  const int64_t nwr = (w + 63) / 64, nstx = (ntx + SUP - 1) / SUP;
-  const int64_t hb = (nty - 1) / SUP, hi = (nty - 1) - hb, vb = (ntx - 1) / SUP;
+  const int64_t nwr = (w + 63) / 64, nstx = (ntx + T::SUP - 1) / T::SUP;
+  const int64_t hb = (nty - 1) / T::SUP, hi = (nty - 1) - hb, vb = (ntx - 1) / T::SUP;
   return hb * nwr * 4 + hi * 2 * nstx + vb * h + 8 * nwr + 2 * (int64_t)h;
 }
 
@@ -1052,7 +1059,7 @@ template <class T>
 __device__ inline int lnode_of(const Work& wk, const ImgDesc& d, int tx0, int ty0, int tx, int ty, u16 slot) {
   (void)wk;
   (void)d;
-  return ((ty - ty0) * SUP + (tx - tx0)) * T::BCAP + slot;
+  return ((ty - ty0) * T::SUP + (tx - tx0)) * T::BCAP + slot;
 }
 
 // threads per super-tile: its items are chains of dependent loads, so more
@@ -1061,7 +1068,7 @@ constexpr int SL_T = 512;
 
 template <class T, class Src>
 __global__ void __launch_bounds__(SL_T) k_seam_local(Src src, Work wk) {
-  constexpr int NL = SUP * SUP * T::BCAP;
+  constexpr int NL = T::SUP * T::SUP * T::BCAP;
   static_assert(NL < 65536 && NL % 2 == 0, "local node index fits 16 bits");
   __shared__ u32 lpw[NL / 2];  // 16-bit entries; 32-bit words for the links
   u16* lp = reinterpret_cast<u16*>(lpw);
@@ -1070,10 +1077,10 @@ __global__ void __launch_bounds__(SL_T) k_seam_local(Src src, Work wk) {
   const ImgDesc& d = src.by_super(gs);
   if (!src.ok(d)) return;
   const int64_t ls = gs - d.s0;
-  const int nstx = (d.ntx + SUP - 1) / SUP;
-  const int tx0 = (int)(ls % nstx) * SUP, ty0 = (int)(ls / nstx) * SUP;
-  const int ntxs = d.ntx - tx0 < SUP ? d.ntx - tx0 : SUP;
-  const int ntys = d.nty - ty0 < SUP ? d.nty - ty0 : SUP;
+  const int nstx = (d.ntx + T::SUP - 1) / T::SUP;
+  const int tx0 = (int)(ls % nstx) * T::SUP, ty0 = (int)(ls / nstx) * T::SUP;
+  const int ntxs = d.ntx - tx0 < T::SUP ? d.ntx - tx0 : T::SUP;
+  const int ntys = d.nty - ty0 < T::SUP ? d.nty - ty0 : T::SUP;
   for (int l = tid; l < NL; l += SL_T) lp[l] = (u16)l;
   __syncthreads();
 
@@ -1135,14 +1142,14 @@ __global__ void __launch_bounds__(SL_T) k_seam_local(Src src, Work wk) {
   // every node of the super-tile points at its local root
   for (int l = tid; l < NL; l += SL_T) {
     const int k = l / T::BCAP, slot = l % T::BCAP;
-    const int tx = tx0 + k % SUP, ty = ty0 + k / SUP;
+    const int tx = tx0 + k % T::SUP, ty = ty0 + k / T::SUP;
     if (tx - tx0 >= ntxs || ty - ty0 >= ntys) continue;
     const int64_t lt = (int64_t)ty * d.ntx + tx;
     if (slot >= wk.nbt[d.tile0 + lt]) continue;
     const u32 r = lroot(lp, (u32)l);
     if (r == (u32)l) continue;
     const int kr = (int)r / T::BCAP, sr = (int)r % T::BCAP;
-    const int64_t ltr = (int64_t)(ty0 + kr / SUP) * d.ntx + tx0 + kr % SUP;
+    const int64_t ltr = (int64_t)(ty0 + kr / T::SUP) * d.ntx + tx0 + kr % T::SUP;
     wk.gpar[tile_node_base<T>(d, lt) + slot] = (int32_t)(tile_node_base<T>(d, ltr) + sr);
   }
 }
@@ -1156,9 +1163,9 @@ __global__ void __launch_bounds__(256) k_border_merge(Src src, Work wk, int64_t 
   int64_t i = gi - d.it0;
   const int nwr = (d.w + 63) >> 6;
   const int ext = (int)d.node0;
-  constexpr int SW = SUP * T::WPR;  // words per super-tile column
-  const int nstx = (d.ntx + SUP - 1) / SUP;
-  const int64_t hb = (d.nty - 1) / SUP, hi = (d.nty - 1) - hb, vb = (d.ntx - 1) / SUP;
+  constexpr int SW = T::SUP * T::WPR;  // words per super-tile column
+  const int nstx = (d.ntx + T::SUP - 1) / T::SUP;
+  const int64_t hb = (d.nty - 1) / T::SUP, hi = (d.nty - 1) - hb, vb = (d.ntx - 1) / T::SUP;
   const int64_t nH = hb * nwr * 4 + hi * 2 * nstx;
   const int64_t nV = vb * d.h;
   if (i < nH) {  // horizontal seam: bottom row of tile row e-1 above top row of tile row e
@@ -1169,7 +1176,7 @@ __global__ void __launch_bounds__(256) k_border_merge(Src src, Work wk, int64_t 
                              // of a word per item (a dense row has up to 32
                              // union points per word, each a chain of finds)
       const int64_t iw = i >> 2;
-      e = SUP * (int)(iw / nwr + 1);
+      e = T::SUP * (int)(iw / nwr + 1);
       jw = (int)(iw % nwr);
       part = 0xFFFFull << (16 * (int)(i & 3));
       inner = false;
@@ -1177,7 +1184,7 @@ __global__ void __launch_bounds__(256) k_border_merge(Src src, Work wk, int64_t 
               // diagonals that leave a super-tile column at its edge words
       const int64_t q = (i - hb * nwr * 4) / (2 * nstx);
       const int r = (int)((i - hb * nwr * 4) % (2 * nstx));
-      e = (int)(q + 1 + q / (SUP - 1));  // the q-th seam index that is not a multiple of SUP
+      e = (int)(q + 1 + q / (T::SUP - 1));  // the q-th seam index that is not a multiple of T::SUP
       jw = (r >> 1) * SW + ((r & 1) ? SW - 1 : 0);
       if (jw >= nwr) return;
       inner = true;
@@ -1217,7 +1224,7 @@ __global__ void __launch_bounds__(256) k_border_merge(Src src, Work wk, int64_t 
   }
   i -= nH;
   if (i < nV) {  // vertical seam on a super-tile column edge, between tile columns e-1 and e, image row y
-    int e = SUP * (int)(i / d.h + 1), y = (int)(i % d.h);
+    int e = T::SUP * (int)(i / d.h + 1), y = (int)(i % d.h);
     int ly = y % T::TH;
     int a = col_bit<T>(wk, d, e - 1, y, true), b = col_bit<T>(wk, d, e, y, false);
     int c = -1, dd = -1;
@@ -1283,7 +1290,7 @@ static_assert(1 << RH_BITS == RH_CAP, "hash width");
 // tiles per workgroup: larger groups send fewer atomics to the roots of
 // components that span many tiles (the exterior above all)
 template <class T>
-constexpr int rh_tiles() { return T::N > 4096 ? 64 : 32; }
+constexpr int rh_tiles() { return T::RHT; }
 constexpr int RH_T = 512;        // threads: finds of many nodes in flight at once
 constexpr int RH_EMPTY = -1;
 
@@ -1885,8 +1892,10 @@ __global__ void __launch_bounds__(T::NT) k_tile_emit(Src src, Work wk) {
   }
 
   // 7. canonical id of every run, in place of the ordinals (values pass
-  // through registers: the two tables overlap)
-  {
+  // through registers: the two tables overlap); only the label image needs
+  // them, without it the ordinals stay and step 8 maps the few it needs
+  const bool lab = d.labels != nullptr;
+  if (lab) {
     constexpr int RPT = (T::N + T::NT - 1) / T::NT;
     int32_t rc[RPT];
 #pragma unroll
@@ -1902,9 +1911,9 @@ __global__ void __launch_bounds__(T::NT) k_tile_emit(Src src, Work wk) {
       if (r >= nruns) break;
       s.rt.rcan[r] = rc[k];
     }
-    if (tid < th) s.lcanon[tid] = lcv;
-    __syncthreads();
   }
+  if (tid < th) s.lcanon[tid] = lcv;
+  __syncthreads();
 
   // 8. colour / parent of border components whose first pixel is here
   for (int c = tid; c < T::NCH; c += T::NT) {
@@ -1920,8 +1929,9 @@ __global__ void __launch_bounds__(T::NT) k_tile_emit(Src src, Work wk) {
       if (d.parent) {
         int x = j * 64 + k;
         int32_t pc;
-        if (x > 0) pc = s.rt.rcan[run_rank(s, ly, x - 1)];
-        else pc = s.lcanon[ly];  // 0 (exterior) at the image's left edge
+        if (x == 0) pc = s.lcanon[ly];  // 0 (exterior) at the image's left edge
+        else if (lab) pc = s.rt.rcan[run_rank(s, ly, x - 1)];
+        else pc = canon_of(s, s.rt.o.ordr[run_rank(s, ly, x - 1)]);
         d.parent[canon] = pc;
       }
     }
@@ -2045,7 +2055,7 @@ inline void place_image(ImgDesc& d, int64_t& tiles, int64_t& nodes, int64_t& cel
   d.it0 = items;
   d.nit = merge_items<T>(d.w, d.h, d.ntx, d.nty);
   d.s0 = supers;
-  supers += (int64_t)((d.ntx + SUP - 1) / SUP) * ((d.nty + SUP - 1) / SUP);
+  supers += (int64_t)((d.ntx + T::SUP - 1) / T::SUP) * ((d.nty + T::SUP - 1) / T::SUP);
   tiles += nt;
   nodes += 1 + nt * T::BCAP;
   cells += nc;
@@ -2074,7 +2084,7 @@ inline void enqueue(Launcher& L, const Src& src, const Work& wk, int64_t tiles, 
   // whatever the other kernels use: it is bound by memory latency and its
   // LDS (not wave slots) limits the workgroups per CU, so wider workgroups
   // keep more waves in flight (measured: faster than 256 and than 1024).
-  using TE = Tile<T::TH, T::TW, (T::N >= 8192 && T::NT < 512 ? 512 : T::NT), T::FG8>;
+  using TE = Tile<T::TH, T::TW, (T::N >= 8192 && T::NT < 512 ? 512 : T::NT), T::FG8, T::SUP, T::RHT>;
   L.launch(k_tile_emit<TE, Src>, tiles, TE::NT, src, wk);
 }
 

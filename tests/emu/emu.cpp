@@ -217,6 +217,8 @@ struct Image {
   int64_t counts[2];
 };
 
+bool no_labels = false;  // EMU_NOLABELS=1: the features-only mode (no label image)
+
 template <class T>
 void run_images(std::vector<Image>& ims, bool batch) {
   for (auto& im : ims) {
@@ -234,7 +236,7 @@ void run_images(std::vector<Image>& ims, bool batch) {
     d.pitch = im.pitch;
     d.w = im.w;
     d.h = im.h;
-    d.labels = im.labels.data();
+    d.labels = no_labels ? nullptr : im.labels.data();
     d.feat = im.feat.data();
     d.parent = im.parent.data();
     d.color = im.color.data();
@@ -242,7 +244,7 @@ void run_images(std::vector<Image>& ims, bool batch) {
     d.counts = im.counts;
     d.flags = 0;
     if ((reinterpret_cast<uintptr_t>(d.img) & 15) == 0 && (d.pitch & 15) == 0) d.flags |= ccl::DF_VEC_IN;
-    if ((reinterpret_cast<uintptr_t>(d.labels) & 15) == 0 && (d.w & 3) == 0) d.flags |= ccl::DF_VEC_LAB;
+    if (d.labels && (reinterpret_cast<uintptr_t>(d.labels) & 15) == 0 && (d.w & 3) == 0) d.flags |= ccl::DF_VEC_LAB;
     return d;
   };
   EmuLauncher L;
@@ -301,6 +303,7 @@ int main(int argc, char** argv) {
       S.rng = strtoull(e, nullptr, 10) * 2 + 1;
     }
   }
+  if (const char* e = getenv("EMU_NOLABELS")) no_labels = strcmp(e, "1") == 0;
   int cfg = atoi(argv[1]);
   switch (cfg) {
     case 0: run_images<ccl::Tile<32, 128>>(ims, batch); break;
@@ -313,6 +316,10 @@ int main(int argc, char** argv) {
     case 7: run_images<ccl::Tile<64, 128>>(ims, batch); break;  // relabeling with 512 threads
     case 8: run_images<ccl::Tile<32, 128, 256, false>>(ims, batch); break;  // 4-adjacent foreground
     case 9: run_images<ccl::Tile<4, 64, 256, false>>(ims, batch); break;
+    // merge schedules: 2 x 2 and 8 x 8 super-tiles, small root-reduction groups
+    case 10: run_images<ccl::Tile<4, 64, 256, true, 2>>(ims, batch); break;
+    case 11: run_images<ccl::Tile<4, 64, 256, true, 8, 4>>(ims, batch); break;
+    case 12: run_images<ccl::Tile<3, 64, 256, true, 8, 1>>(ims, batch); break;
     default: fprintf(stderr, "bad tile config\n"); return 2;
   }
   FILE* fo = fopen(argv[4], "wb");

@@ -27,8 +27,10 @@ EXE = os.path.join(BUILD, "ccl_emu")
 CXX = "/opt/rocm/llvm/bin/clang++" if os.path.exists("/opt/rocm/llvm/bin/clang++") else "clang++"
 
 # tile configurations compiled into the emulator: (rows, columns)
-TILES = {0: (32, 128), 1: (4, 64), 2: (3, 64), 3: (5, 192), 4: (64, 64), 5: (1, 64), 6: (16, 128), 7: (64, 128), 8: (32, 128), 9: (4, 64)}
-# 6: 512 threads; 7: 256, relabeling 512; 8, 9: 4-adjacent foreground, 8-adjacent background
+TILES = {0: (32, 128), 1: (4, 64), 2: (3, 64), 3: (5, 192), 4: (64, 64), 5: (1, 64), 6: (16, 128), 7: (64, 128), 8: (32, 128),
+         9: (4, 64), 10: (4, 64), 11: (4, 64), 12: (3, 64)}
+# 6: 512 threads; 7: 256, relabeling 512; 8, 9: 4-adjacent foreground, 8-adjacent background;
+# 10: 2 x 2 super-tiles; 11: 8 x 8 super-tiles, 4 tiles per root-reduction group; 12: 8 x 8, one tile per group
 
 
 def build(force: bool = False) -> str:
@@ -58,11 +60,14 @@ class EmuResult:
     euler: int
 
 
-def run(images, tile_cfg: int = 0, batch: bool = False, pitch_pad: int = 0, sched: str = "fwd"):
+def run(images, tile_cfg: int = 0, batch: bool = False, pitch_pad: int = 0, sched: str = "fwd",
+        labels: bool = True):
     """Label a list of 2-D uint8 arrays with the emulated kernels.
 
     sched: order in which the threads of a workgroup run after a barrier
-    ("fwd", "rev", or a decimal seed for a pseudo-random order)."""
+    ("fwd", "rev", or a decimal seed for a pseudo-random order).
+    labels=False: the features-only mode (no label image is written; the
+    returned labels keep the fill value -7)."""
     exe = build()
     with tempfile.TemporaryDirectory() as td:
         fin, fout = os.path.join(td, "in.bin"), os.path.join(td, "out.bin")
@@ -76,7 +81,8 @@ def run(images, tile_cfg: int = 0, batch: bool = False, pitch_pad: int = 0, sche
                 f.write(struct.pack("<iiq", w, h, pitch))
                 f.write(buf.tobytes())
         env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
-                   UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1", EMU_SCHED=str(sched))
+                   UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1", EMU_SCHED=str(sched),
+                   EMU_NOLABELS="0" if labels else "1")
         p = subprocess.run([exe, str(tile_cfg), "batch" if batch else "single", fin, fout],
                            capture_output=True, text=True, env=env)
         if p.returncode != 0:

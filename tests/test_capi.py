@@ -88,11 +88,13 @@ def test_variants_are_described():
     assert n >= 2
     seen = set()
     for v in range(n):
-        th, tw, hs, nt = _capi.variant_info(v)
+        th, tw, hs, nt, sup, rg = _capi.variant_info(v)
         assert th >= 1 and tw % 64 == 0 and nt % 64 == 0
-        seen.add((th, tw, hs, nt))
+        assert 2 <= sup <= 8 and 1 <= rg <= 64 and (hs or rg == 1)
+        seen.add((th, tw, hs, nt, sup, rg))
         assert _capi.workspace_bytes(1000, 700, v) > 0
     assert len(seen) == n
+    assert {x[4] for x in seen} >= {2, 4, 8}  # merge schedules on offer
     assert _capi.variant_info(0)[:2] == _capi.tile_shape()
     with pytest.raises(_capi.CclError):
         _capi.variant_info(n)

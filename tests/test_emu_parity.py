@@ -86,3 +86,32 @@ def test_emulated_kernels_complementary_connectivity(cfg):
     imgs = _cases(300 + cfg, 6, 30, 200)
     for img, r in zip(imgs, emu_runner.run(imgs, tile_cfg=cfg, batch=True, pitch_pad=3)):
         _assert_same(img, r, fg8=False)
+
+
+@pytest.mark.parametrize("cfg,batch", [(0, False), (7, False), (1, True), (8, False)])
+def test_emulated_features_only(cfg, batch):
+    """No label image (labels = NULL): every table equal to the oracle's, and
+    the label buffer left untouched."""
+    imgs = _cases(400 + cfg, 6, 40, 300) + [synth.bernoulli_blocks(128, 512, 0.5, 1, 8)]
+    fg8 = cfg != 8
+    for img, r in zip(imgs, emu_runner.run(imgs, tile_cfg=cfg, batch=batch, labels=False)):
+        o = oracle.label(img, fg8=fg8)
+        assert r.n_labels == o.n_labels and r.euler == o.euler
+        assert np.all(r.labels == -7)
+        assert np.array_equal(r.parent, o.parent)
+        assert np.array_equal(r.color, o.color)
+        assert np.array_equal(r.bbox, o.bbox)
+        assert np.array_equal(r.S, o.S) and np.array_equal(r.Sx, o.Sx) and np.array_equal(r.Sy, o.Sy)
+
+
+@pytest.mark.parametrize("cfg", [10, 11, 12])
+def test_emulated_merge_schedules(cfg):
+    """Super-tiles of 2 x 2 and 8 x 8 tiles (the seams k_seam_local merges in
+    LDS against those left to k_border_merge move) and root-reduction groups
+    of 4 and 1 tiles, single and batched."""
+    imgs = _cases(500 + cfg, 8, 60, 700)
+    for img, r in zip(imgs, emu_runner.run(imgs, tile_cfg=cfg)):
+        _assert_same(img, r)
+    imgs = _cases(600 + cfg, 6, 50, 400)
+    for img, r in zip(imgs, emu_runner.run(imgs, tile_cfg=cfg, batch=True, pitch_pad=7)):
+        _assert_same(img, r)

@@ -57,7 +57,7 @@ def test_every_variant_single_image_matches_oracle():
             _same(r, o)
 
 
-@pytest.mark.parametrize("variant", range(8))
+@pytest.mark.parametrize("variant", range(13))
 def test_batch_matches_oracle_per_image(variant):
     import paper_2006_09299_amd as ccl
     if variant >= ccl.num_variants():
