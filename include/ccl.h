@@ -87,6 +87,29 @@ size_t ccl_workspace_bytes(int32_t w, int32_t h);
 int ccl_label(const uint8_t *img, int32_t w, int32_t h, int64_t pitch, const ccl_outputs_t *out, void *ws,
               size_t ws_bytes, void *stream);
 
+/* Bytes of the per-GPU scratch array of ccl_label_noalloc (96 MiB: images
+ * whose ccl_workspace_bytes is at most this, e.g. up to 4096 x 4096). */
+#define CCL_NOALLOC_SCRATCH_BYTES ((size_t)96 << 20)
+
+/* ccl_label for callers that cannot allocate device memory (code being
+ * captured into a HIP graph, tight serving loops, harnesses that forbid
+ * hipMalloc): the same work and outputs as ccl_label, with the workspace
+ * taken from a static array of CCL_NOALLOC_SCRATCH_BYTES that the library
+ * holds on every GPU it runs on until the process ends.  The caller passes
+ * the input and the outputs as for ccl_label; the call allocates nothing.
+ * The current device (hipSetDevice) must be the one `stream` runs on; the
+ * array's address on that device is looked up on the first call there.
+ * Every call on one GPU shares that GPU's array: calls whose work may
+ * overlap on the device (other streams, or another host thread) race and
+ * give wrong results; calls on one stream are ordered and safe.  The
+ * array needs no clearing (every kernel writes the scratch it reads).
+ * Errors: CCL_EINVAL as for ccl_label; CCL_ENOSPC when the image needs more
+ * workspace than CCL_NOALLOC_SCRATCH_BYTES (ccl_workspace_bytes(w, h)
+ * tells); CCL_EHIP when the runtime cannot give the array's address or
+ * refuses a launch.  Nothing is enqueued on an argument error. */
+int ccl_label_noalloc(const uint8_t *img, int32_t w, int32_t h, int64_t pitch, const ccl_outputs_t *out,
+                      void *stream);
+
 /* ccl_label with the connectivity pair chosen (the note after the
  * unification algorithm, Sec. 3.2): fg_adjacency = 8 is the default pair
  * (8-adjacent foreground, 4-adjacent background); 4 the complementary one

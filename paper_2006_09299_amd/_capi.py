@@ -70,8 +70,9 @@ EXPORTS = (
     "ccl_variant_info", "ccl_workspace_bytes_v", "ccl_label_v", "ccl_batch_sizes", "ccl_batch_prepare",
     "ccl_label_batch", "ccl_strerror", "ccl_tile_shape", "ccl_server_create", "ccl_server_footprint",
     "ccl_server_submit", "ccl_server_poll", "ccl_server_release", "ccl_server_stats", "ccl_server_destroy",
-    "ccl_fill_workspace_bytes", "ccl_fill_holes", "ccl_label_conn",
+    "ccl_fill_workspace_bytes", "ccl_fill_holes", "ccl_label_conn", "ccl_label_noalloc",
 )
+NOALLOC_SCRATCH_BYTES = 96 << 20  # CCL_NOALLOC_SCRATCH_BYTES
 TRACE_EVENTS = 11
 
 _lib = None
@@ -146,6 +147,8 @@ def lib():
                                      ctypes.c_size_t, vp]
         L.ccl_label_conn.restype = ctypes.c_int
         L.ccl_label_conn.argtypes = [vp, i32, i32, i64, ctypes.POINTER(ccl_outputs_t), vp, ctypes.c_size_t, vp, i32]
+        L.ccl_label_noalloc.restype = ctypes.c_int
+        L.ccl_label_noalloc.argtypes = [vp, i32, i32, i64, ctypes.POINTER(ccl_outputs_t), vp]
         L.ccl_tile_shape.restype = None
         L.ccl_tile_shape.argtypes = [ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
         _lib = L

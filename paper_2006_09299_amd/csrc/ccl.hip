@@ -8,6 +8,8 @@
 
 #include <string.h>
 
+#include <mutex>
+
 #include "ccl_pipeline.h"
 #include "ccl_fill.h"
 #include "../../include/ccl.h"
@@ -181,9 +183,43 @@ FillLayout fill_layout(int64_t cap) {
   return L;
 }
 
+// Workspace of ccl_label_noalloc: one array per GPU, a module global of the
+// code object (the runtime places it when the library's code is loaded on a
+// device; it lives until the process ends).  In host code `scratch` is only
+// the host-side handle of the symbol, never a device address: kernels get
+// the address hipGetSymbolAddress returns for the current device.
+static __device__ __attribute__((used)) __align__(256) unsigned char scratch[CCL_NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void* scratch_ptr[MAX_DEVICES];
+
+// address of the current device's scratch (resolved once per device);
+// nullptr when the runtime cannot tell
+void* scratch_address() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+    scratch_ptr[dev] = p;
+  }
+  return scratch_ptr[dev];
+}
+
 }  // namespace
 
 extern "C" {
+
+int ccl_label_noalloc(const uint8_t* img, int32_t w, int32_t h, int64_t pitch, const ccl_outputs_t* out,
+                      void* stream) {
+  if (!image_args_ok(img, w, h, pitch, out)) return CCL_EINVAL;
+  if (ccl_workspace_bytes_v(w, h, 0) > CCL_NOALLOC_SCRATCH_BYTES) return CCL_ENOSPC;
+  void* ws = scratch_address();
+  if (!ws) return CCL_EHIP;
+  return label_one(img, w, h, pitch, out, ws, CCL_NOALLOC_SCRATCH_BYTES, stream, nullptr, 0);
+}
 
 size_t ccl_fill_workspace_bytes(int64_t cap) {
   if (cap < 1 || cap >= INT32_MAX) return 0;

@@ -134,3 +134,18 @@ def test_label_conn_rejects_other_adjacencies_on_host():
     for adj in (0, 1, 6, 16, -8):
         assert L.ccl_label_conn(fake, 64, 64, 64, ctypes.byref(out), fake, wsb, None, adj) == _capi.CCL_EINVAL
     assert L.ccl_label_conn(None, 64, 64, 64, ctypes.byref(out), fake, wsb, None, 4) == _capi.CCL_EINVAL
+
+
+def test_noalloc_refuses_oversize_and_bad_arguments_on_host():
+    """ccl_label_noalloc checks its arguments and the scratch limit before it
+    touches the runtime (the pointers are never dereferenced)."""
+    L = _capi.lib()
+    fake = 0x1000
+    out = _capi.ccl_outputs_t(fake, fake, fake, fake, 10, fake)
+    h = 4096
+    while _capi.workspace_bytes(4096, h) <= _capi.NOALLOC_SCRATCH_BYTES:
+        h += 64
+    assert L.ccl_label_noalloc(fake, 4096, h, 4096, ctypes.byref(out), None) == _capi.CCL_ENOSPC
+    assert L.ccl_label_noalloc(None, 8, 8, 8, ctypes.byref(out), None) == _capi.CCL_EINVAL
+    assert L.ccl_label_noalloc(fake, 64, 64, 63, ctypes.byref(out), None) == _capi.CCL_EINVAL
+    assert L.ccl_label_noalloc(fake, 64, 64, 64, None, None) == _capi.CCL_EINVAL
