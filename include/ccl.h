@@ -120,8 +120,8 @@ int ccl_label_conn(const uint8_t *img, int32_t w, int32_t h, int64_t pitch, cons
                    size_t ws_bytes, void *stream, int32_t fg_adjacency);
 
 /* Number of HIP events ccl_label_traced records: one before each of the
- * path's ten kernels, in launch order, and one after the last. */
-#define CCL_TRACE_EVENTS 11
+ * path's nine kernels, in launch order, and one after the last. */
+#define CCL_TRACE_EVENTS 10
 
 /* Same work as ccl_label, with `events` [host array of CCL_TRACE_EVENTS
  * hipEvent_t created by the caller] recorded on `stream` around every kernel,

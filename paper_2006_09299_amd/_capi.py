@@ -73,7 +73,7 @@ EXPORTS = (
     "ccl_fill_workspace_bytes", "ccl_fill_holes", "ccl_label_conn", "ccl_label_noalloc",
 )
 NOALLOC_SCRATCH_BYTES = 96 << 20  # CCL_NOALLOC_SCRATCH_BYTES
-TRACE_EVENTS = 11
+TRACE_EVENTS = 10
 
 _lib = None
 

@@ -329,7 +329,7 @@ int ccl_label_traced(const uint8_t* img, int32_t w, int32_t h, int64_t pitch, co
 const char* ccl_kernel_name(int k) {
   static const char* names[CCL_TRACE_EVENTS - 1] = {
       "k_tile_export", "k_seam_local", "k_border_merge", "k_reduce_roots", "k_leaders",
-      "k_scan_reduce", "k_scan_apply", "k_emit_border", "k_node_canon", "k_tile_emit"};
+      "k_scan_reduce", "k_scan_apply", "k_border_canon", "k_tile_emit"};
   return k >= 0 && k < CCL_TRACE_EVENTS - 1 ? names[k] : nullptr;
 }
 

@@ -47,8 +47,8 @@
 //                   in raster order -> canonical id base of every such cell
 //                   (block totals; then every block adds the totals of the
 //                   image's earlier blocks and scans its own cells).
-//   k_emit_border : canonical id and features of components crossing tiles.
-//   k_node_canon  : canonical id of every border node.
+//   k_border_canon: canonical id of every border node; features of the
+//                   components crossing tiles.
 //   k_tile_emit   : from the tile state: canonical id of every run, the label
 //                   image, features / colour / parent of every component the
 //                   tile owns and its Euler number contribution.
@@ -120,16 +120,16 @@ struct Work {
   int32_t* gkey;     // [nodes] raster index of the node's first pixel
   int32_t* gminkey;  // [nodes] at roots: minimum key of the class
   int32_t* grank;    // [nodes] bits 0-15 rank / interior-before, 16-21 row, 31 leader
-  int32_t* rcanon;   // [nodes] at roots: canonical id
+  int32_t* rcanon;   // [nodes] at roots: rank of the component among those starting in its first pixel's cell
   int32_t* ncanon;   // [nodes] canonical id of the node's component
   Feature* gacc;     // [nodes] partial features; at roots the class sum
   int32_t* nbt;      // [tiles] border nodes per tile
-  u16* bidx_top;     // [tiles*TW] border node index of every top-row pixel
-  u16* bidx_bot;     // [tiles*TW]
-  u16* bidx_left;    // [tiles*TH]
-  u16* bidx_right;   // [tiles*TH]
-  u64* bits_top;     // [tiles*WPR] foreground bits of the top row
-  u64* bits_bot;     // [tiles*WPR]
+  // border arrays, the two sides of a tile next to each other (indexed by
+  // side rather than by pointer: a per-lane choice of pointer makes the
+  // compiler load it from the kernel arguments through vector memory)
+  u16* bidx_h;       // [tiles][2][TW] border node index of every top (0) / bottom (1) row pixel
+  u16* bidx_v;       // [tiles][2][TH] left (0) / right (1) column
+  u64* bits_h;       // [tiles][2][WPR] foreground bits of the top / bottom row
   u64* bits_lr;      // [tiles*2] left column (bit = row), right column
   int32_t* cgrid;    // [sum h*ntx] per (row, tile column): starts, then base ids
   int32_t* bsum;     // [scan blocks]
@@ -219,9 +219,23 @@ __device__ inline void st_ag(int32_t* p, int v) { __hip_atomic_store(p, v, __ATO
 __device__ inline u32 ld16(const u16* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
 __device__ inline void st16(u16* p, u32 v) { __hip_atomic_store(p, (u16)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
 
+// Where entry i lives: the identity, or (tile union-find over positions)
+// bits 1-3 of the position XORed with bits 7-9, so that the lanes of a wave,
+// which hold consecutive 16-pixel chunks of several rows and touch the same
+// offset in each, reach different LDS banks.  Bit 0 is kept: the two entries
+// of a 32-bit word stay together (linking swaps one of them by CAS).
+struct IdMap {
+  __device__ u32 operator()(u32 i) const { return i; }
+};
+struct SwzMap {
+  __device__ u32 operator()(u32 i) const { return i ^ (((i >> 7) & 7u) << 1); }
+};
+__device__ inline u32 swz(u32 p) { return SwzMap()(p); }
+
 // link root b under a; false if b is no longer a root
-__device__ inline bool llink(u16* par, u32 a, u32 b) {
-  u32* w = reinterpret_cast<u32*>(par + (b & ~1u));
+template <class M = IdMap>
+__device__ inline bool llink(u16* par, u32 a, u32 b, M m = M()) {
+  u32* w = reinterpret_cast<u32*>(par + (m(b) & ~1u));
   const int sh = (int)(b & 1u) * 16;
   u32 old = ld_wg(w);
   for (;;) {
@@ -235,13 +249,14 @@ __device__ inline bool llink(u16* par, u32 a, u32 b) {
 // unite the classes of a and b: both walks advance together, two levels
 // per step with path halving; the loads are unconditional (a walk that has
 // reached its root reads it again) so that the four of a step overlap
-__device__ inline void lunion(u16* par, u32 a, u32 b) {
+template <class M = IdMap>
+__device__ inline void lunion(u16* par, u32 a, u32 b, M m = M()) {
   for (;;) {
     for (;;) {
-      u32 pa = ld16(par + a), pb = ld16(par + b);
-      u32 ga = ld16(par + pa), gb = ld16(par + pb);
-      if (ga != pa) st16(par + a, ga);  // a is not a root: halve
-      if (gb != pb) st16(par + b, gb);
+      u32 pa = ld16(par + m(a)), pb = ld16(par + m(b));
+      u32 ga = ld16(par + m(pa)), gb = ld16(par + m(pb));
+      if (ga != pa) st16(par + m(a), ga);  // a is not a root: halve
+      if (gb != pb) st16(par + m(b), gb);
       const bool fa = ga == pa, fb = gb == pb;  // pa / pb is a root
       a = ga;
       b = gb;
@@ -253,15 +268,16 @@ __device__ inline void lunion(u16* par, u32 a, u32 b) {
       a = b;
       b = t;
     }
-    if (llink(par, a, b)) return;  // else b was linked meanwhile: retry
+    if (llink(par, a, b, m)) return;  // else b was linked meanwhile: retry
   }
 }
 // read-only walk to the root (no writes)
-__device__ inline u32 lroot(const u16* par, u32 x) {
-  u32 p = ld16(par + x);
+template <class M = IdMap>
+__device__ inline u32 lroot(const u16* par, u32 x, M m = M()) {
+  u32 p = ld16(par + m(x));
   while (p != x) {
     x = p;
-    p = ld16(par + x);
+    p = ld16(par + m(x));
   }
   return x;
 }
@@ -451,8 +467,13 @@ __device__ inline TileGeom tile_geom(const ImgDesc& d, int64_t gt) {
 template <class T>
 struct TileFetch {
   static constexpr int K = (T::NCH + T::NT - 1) / T::NT;
+  // a wave's first lane holds a chunk that starts a row unless the chunks of
+  // a row do not divide 64 (then it reads the byte before its chunk); the
+  // byte loads are issued after all vector loads (each load's use waits for
+  // every earlier one)
+  static constexpr bool PREV = 64 % T::CPR != 0;
   uint4 v[K];
-  u32 prevb[K];
+  u32 prevb[PREV ? K : 1];
 };
 
 template <class T>
@@ -469,7 +490,16 @@ __device__ inline void tile_fetch(TileFetch<T>& f, const ImgDesc& d, const TileG
     v.x = v.y = v.z = v.w = 0u;
     if (in && vec_in && cx + 16 <= g.tw) v = *reinterpret_cast<const uint4*>(src);
     f.v[k] = v;
-    f.prevb[k] = in && cx > 0 && (tid & 63) == 0 ? (u32)src[-1] : 0u;
+  }
+  if constexpr (TileFetch<T>::PREV) {
+#pragma unroll
+    for (int k = 0; k < TileFetch<T>::K; k++) {
+      const int c = k * T::NT + tid;
+      const int ly = c / T::CPR, cx = (c % T::CPR) * 16;
+      const bool in = c < T::NCH && ly < g.th && cx < g.tw;
+      const u8* src = d.img + (int64_t)(g.y0 + ly) * d.pitch + (g.x0 + cx);
+      f.prevb[k] = in && cx > 0 && (tid & 63) == 0 ? (u32)src[-1] : 0u;
+    }
   }
 }
 
@@ -512,14 +542,14 @@ __device__ int tile_pack(TileSmem<T>& s, const TileFetch<T>& f, const ImgDesc& d
     if (in) {
       u32 carry;
       if (cc == 0) carry = ~m & 1u;
-      else if ((tid & 63) == 0) carry = f.prevb[k] != 0u;
+      else if (TileFetch<T>::PREV && (tid & 63) == 0) carry = f.prevb[TileFetch<T>::PREV ? k : 0] != 0u;
       else carry = prev >> 15;
       const u32 vm = (u32)valid_mask(0, tw - cx) & 0xFFFFu;
       e = (m ^ ((m << 1) | carry)) & vm;
       all0 = all0 && (m & vm) == 0;
       all1 = all1 && (m & vm) == vm;
       const u32 p0 = (u32)(ly * T::TW + cx);
-      for (u32 t = e; t; t &= t - 1) s.par[p0 + (u32)ctz32(t)] = (u16)(p0 + (u32)ctz32(t));
+      for (u32 t = e; t; t &= t - 1) s.par[swz(p0 + (u32)ctz32(t))] = (u16)(p0 + (u32)ctz32(t));
     }
     reinterpret_cast<u16*>(s.st)[c] = (u16)e;
   }
@@ -571,7 +601,8 @@ __device__ void tile_unite(TileSmem<T>& s, u32* stage_all, int stage_words, int 
         pts &= pts - 1;
         const int x = xb + (kk & 15);
         const int xu = x + (kk >> 4 == 1) - (kk >> 4 == 2);
-        lunion(s.par, (u32)(ly * T::TW + run_start(s, ly, x)), (u32)((ly - 1) * T::TW + run_start(s, ly - 1, xu)));
+        lunion(s.par, (u32)(ly * T::TW + run_start(s, ly, x)), (u32)((ly - 1) * T::TW + run_start(s, ly - 1, xu)),
+               SwzMap());
       }
       continue;
     }
@@ -598,59 +629,37 @@ __device__ void tile_unite(TileSmem<T>& s, u32* stage_all, int stage_words, int 
         const u32 e = stage[i];
         const int x = (int)(e & 1023u), row = (int)((e >> 10) & 63u), kind = (int)(e >> 16);
         const int xu = x + (kind == 1) - (kind == 2);
-        lunion(s.par, (u32)(row * T::TW + run_start(s, row, x)), (u32)((row - 1) * T::TW + run_start(s, row - 1, xu)));
+        lunion(s.par, (u32)(row * T::TW + run_start(s, row, x)), (u32)((row - 1) * T::TW + run_start(s, row - 1, xu)),
+               SwzMap());
       }
       wave_sync();  // the list is rewritten next round
     }
   }
   __syncthreads();
 
-  // 3. flatten: every run start points at its root (own entry written only)
+  // 3. flatten: every run start points at its root (own entry written
+  // only); root masks; the roots of components touching the tile border
+  // (runs of the first and last rows, each row's first run and its last
+  // run, which holds the last pixel) are flagged
   for (int c = tid; c < T::NCH; c += T::NT) {
-    int ly = c / T::CPR, cc = c % T::CPR;
-    if (ly >= th) continue;
-    int j = cc >> 2, sh = (cc & 3) * 16;
-    u32 m = (u32)(s.st[ly * T::WPR + j] >> sh) & 0xFFFFu;
-    while (m) {
-      u32 p = (u32)(ly * T::TW + j * 64 + sh + ctz32(m));
-      m &= m - 1;
-      st16(&s.par[p], lroot(s.par, p));
-    }
-  }
-  __syncthreads();
-
-  // 4. roots of components touching the tile border; root masks
-  for (int t = tid; t < 2 * T::CPR + 2 * T::TH; t += T::NT) {
-    if (t < 2 * T::CPR) {  // top / bottom row, one chunk each
-      int ly = t < T::CPR ? 0 : th - 1;
-      int cc = t % T::CPR;
-      int j = cc >> 2, sh = (cc & 3) * 16;
-      u32 m = (u32)(s.st[ly * T::WPR + j] >> sh) & 0xFFFFu;
-      while (m) {
-        u32 p = (u32)(ly * T::TW + j * 64 + sh + ctz32(m));
-        m &= m - 1;
-        u32 r = s.par[p];
-        atomicOr(&s.bflag[r >> 6], 1ull << (r & 63));
-      }
-    } else {
-      int k = t - 2 * T::CPR;
-      int ly = k % T::TH;
-      if (ly >= th) continue;
-      int x = k < T::TH ? 0 : run_start(s, ly, tw - 1);
-      u32 r = s.par[ly * T::TW + x];
-      atomicOr(&s.bflag[r >> 6], 1ull << (r & 63));
-    }
-  }
-  for (int c = tid; c < T::NCH; c += T::NT) {
-    int ly = c / T::CPR, cc = c % T::CPR;
-    int j = cc >> 2, sh = (cc & 3) * 16;
-    u32 m = ly < th ? (u32)(s.st[ly * T::WPR + j] >> sh) & 0xFFFFu : 0u;
+    const int ly = c / T::CPR, cc = c % T::CPR;
+    const int j = cc >> 2, sh = (cc & 3) * 16;
+    const u64* strow = &s.st[ly * T::WPR];
+    u32 m = ly < th ? (u32)(strow[j] >> sh) & 0xFFFFu : 0u;
+    // the row's last run starts in this chunk when no start follows it
+    bool later = sh < 48 && (strow[j] >> (sh + 16)) != 0ull;
+    for (int jj = j + 1; jj < T::WPR; jj++) later = later || strow[jj] != 0ull;
+    const u32 last = m && !later ? 1u << (31 - __builtin_clz(m)) : 0u;
+    const u32 edge = ly == 0 || ly == th - 1 ? 0xFFFFu : ((cc == 0 ? 1u : 0u) | last);
     u32 rm = 0;
     while (m) {
-      int k = ctz32(m);
+      const int k = ctz32(m);
       m &= m - 1;
-      u32 p = (u32)(ly * T::TW + j * 64 + sh + k);
-      if (s.par[p] == p) rm |= 1u << k;
+      const u32 p = (u32)(ly * T::TW + j * 64 + sh + k);
+      const u32 r = lroot(s.par, p, SwzMap());
+      if (r == p) rm |= 1u << k;
+      else st16(&s.par[swz(p)], r);
+      if ((edge >> k) & 1u) atomicOr(&s.bflag[r >> 6], 1ull << (r & 63));
     }
     reinterpret_cast<u16*>(s.rootm)[c] = (u16)rm;
   }
@@ -858,17 +867,17 @@ __device__ void export_tile(TileSmem<T>& s, Acc* bacc, const ImgDesc& d, const T
     for (int t = tid; t < 2 * T::TW + 2 * T::TH; t += T::NT) {
       if (t < 2 * T::TW) {
         int x = t % T::TW;
-        (t >= T::TW ? wk.bidx_bot : wk.bidx_top)[gt * T::TW + x] = x < tw ? (u16)0 : (u16)0xFFFFu;
+        wk.bidx_h[gt * 2 * T::TW + t] = x < tw ? (u16)0 : (u16)0xFFFFu;
       } else {
         int k = t - 2 * T::TW;
         int ly = k % T::TH;
-        (k >= T::TH ? wk.bidx_right : wk.bidx_left)[gt * T::TH + ly] = ly < th ? (u16)0 : (u16)0xFFFFu;
+        wk.bidx_v[gt * 2 * T::TH + k] = ly < th ? (u16)0 : (u16)0xFFFFu;
       }
     }
     for (int t = tid; t < 2 * T::WPR + 2; t += T::NT) {
       if (t < 2 * T::WPR) {
         int j = t % T::WPR;
-        (t >= T::WPR ? wk.bits_bot : wk.bits_top)[gt * T::WPR + j] = col ? valid_mask(j, tw) : 0ull;
+        wk.bits_h[gt * 2 * T::WPR + t] = col ? valid_mask(j, tw) : 0ull;
       } else {
         wk.bits_lr[gt * 2 + (t - 2 * T::WPR)] = col ? low_mask(th) : 0ull;
       }
@@ -892,9 +901,9 @@ __device__ void export_tile(TileSmem<T>& s, Acc* bacc, const ImgDesc& d, const T
     int rank = s.spre[wd] + popc64(stw & low_mask(sh));
     for (u32 m = (u32)(stw >> sh) & 0xFFFFu; m; m &= m - 1) {
       int p = ly * T::TW + j * 64 + sh + ctz32(m);
-      u32 r = s.par[p];
+      u32 r = s.par[swz(p)];
       int o = ((s.bflag[r >> 6] >> (r & 63)) & 1ull) ? bidx_of<T>(s, (int)r) : nb + iord_of<T>(s, (int)r);
-      s.par[p] = (u16)o;  // only this thread reads this entry from here on
+      s.par[swz(p)] = (u16)o;  // only this thread reads this entry from here on
       to[rank++] = (u16)o;
     }
     const u64 bmw = s.rootm[wd] & s.bflag[wd];
@@ -935,7 +944,7 @@ __device__ void export_tile(TileSmem<T>& s, Acc* bacc, const ImgDesc& d, const T
     RowSum rs;
     rs.o = -1;
     for_segments<T>(s, ly, cc, tw, [&](int start, int a, int b) {
-      int o = s.par[ly * T::TW + start];
+      int o = s.par[swz(ly * T::TW + start)];
       if (o < nb) rowsum_add(rs, bacc, o, ly, a, b);
     });
     rowsum_flush(rs, bacc, ly);
@@ -959,20 +968,19 @@ __device__ void export_tile(TileSmem<T>& s, Acc* bacc, const ImgDesc& d, const T
       int x = t % T::TW;
       int ly = bottom ? th - 1 : 0;
       u16 v = 0xFFFFu;
-      if (x < tw) v = s.par[ly * T::TW + run_start(s, ly, x)];
-      (bottom ? wk.bidx_bot : wk.bidx_top)[gt * T::TW + x] = v;
+      if (x < tw) v = s.par[swz(ly * T::TW + run_start(s, ly, x))];
+      wk.bidx_h[gt * 2 * T::TW + t] = v;
     } else {
       int k = t - 2 * T::TW;
       int right = k >= T::TH;
       int ly = k % T::TH;
       u16 v = 0xFFFFu;
-      if (ly < th) v = s.par[ly * T::TW + (right ? run_start(s, ly, tw - 1) : 0)];
-      (right ? wk.bidx_right : wk.bidx_left)[gt * T::TH + ly] = v;
+      if (ly < th) v = s.par[swz(ly * T::TW + (right ? run_start(s, ly, tw - 1) : 0))];
+      wk.bidx_v[gt * 2 * T::TH + k] = v;
     }
   }
   for (int t = tid; t < 2 * T::WPR; t += T::NT) {
-    if (t < T::WPR) wk.bits_top[gt * T::WPR + t] = s.bits[t];
-    else wk.bits_bot[gt * T::WPR + (t - T::WPR)] = s.bits[(th - 1) * T::WPR + (t - T::WPR)];
+    wk.bits_h[gt * 2 * T::WPR + t] = t < T::WPR ? s.bits[t] : s.bits[(th - 1) * T::WPR + (t - T::WPR)];
   }
   // left / right column bits (bit = row): one lane per row of waves 0 / 1
   if (tid < 128) {
@@ -1010,21 +1018,21 @@ __device__ inline u64 seam_bits(const Work& wk, const ImgDesc& d, int tile_row, 
   if (jw < 0 || jw >= nwr) return 0ull;
   int tcol = jw / T::WPR, j = jw % T::WPR;
   int64_t gt = d.tile0 + (int64_t)tile_row * d.ntx + tcol;
-  return (bottom ? wk.bits_bot : wk.bits_top)[gt * T::WPR + j];
+  return wk.bits_h[(gt * 2 + (bottom ? 1 : 0)) * T::WPR + j];
 }
 template <class T>
 __device__ inline int seam_node(const Work& wk, const ImgDesc& d, int tile_row, int x, bool bottom) {
   int tcol = x / T::TW;
   int64_t lt = (int64_t)tile_row * d.ntx + tcol;
   int64_t gt = d.tile0 + lt;
-  u16 b = (bottom ? wk.bidx_bot : wk.bidx_top)[gt * T::TW + (x % T::TW)];
+  u16 b = wk.bidx_h[(gt * 2 + (bottom ? 1 : 0)) * T::TW + (x % T::TW)];
   return (int)(tile_node_base<T>(d, lt) + b);
 }
 template <class T>
 __device__ inline int col_node(const Work& wk, const ImgDesc& d, int tcol, int y, bool right) {
   int64_t lt = (int64_t)(y / T::TH) * d.ntx + tcol;
   int64_t gt = d.tile0 + lt;
-  u16 b = (right ? wk.bidx_right : wk.bidx_left)[gt * T::TH + (y % T::TH)];
+  u16 b = wk.bidx_v[(gt * 2 + (right ? 1 : 0)) * T::TH + (y % T::TH)];
   return (int)(tile_node_base<T>(d, lt) + b);
 }
 template <class T>
@@ -1113,8 +1121,8 @@ __global__ void __launch_bounds__(SL_T) k_seam_local(Src src, Work wk) {
         if (xu < xs0 || xu >= xs1) continue;  // leaves the super-tile: k_border_merge
         const int64_t gl = d.tile0 + (int64_t)e * d.ntx + x / T::TW;
         const int64_t gu = d.tile0 + (int64_t)(e - 1) * d.ntx + xu / T::TW;
-        const int a = lnode_of<T>(wk, d, tx0, ty0, x / T::TW, e, wk.bidx_top[gl * T::TW + x % T::TW]);
-        const int b = lnode_of<T>(wk, d, tx0, ty0, xu / T::TW, e - 1, wk.bidx_bot[gu * T::TW + xu % T::TW]);
+        const int a = lnode_of<T>(wk, d, tx0, ty0, x / T::TW, e, wk.bidx_h[gl * 2 * T::TW + x % T::TW]);
+        const int b = lnode_of<T>(wk, d, tx0, ty0, xu / T::TW, e - 1, wk.bidx_h[(gu * 2 + 1) * T::TW + xu % T::TW]);
         lunion(lp, (u32)a, (u32)b);
       }
     } else {
@@ -1128,8 +1136,8 @@ __global__ void __launch_bounds__(SL_T) k_seam_local(Src src, Work wk) {
         dd = col_bit<T>(wk, d, e, y - 1, false);
       }
       const int64_t gL = d.tile0 + (int64_t)ty * d.ntx + (e - 1), gR = d.tile0 + (int64_t)ty * d.ntx + e;
-      auto left = [&](int yy) { return lnode_of<T>(wk, d, tx0, ty0, e - 1, ty, wk.bidx_right[gL * T::TH + yy % T::TH]); };
-      auto right = [&](int yy) { return lnode_of<T>(wk, d, tx0, ty0, e, ty, wk.bidx_left[gR * T::TH + yy % T::TH]); };
+      auto left = [&](int yy) { return lnode_of<T>(wk, d, tx0, ty0, e - 1, ty, wk.bidx_v[(gL * 2 + 1) * T::TH + yy % T::TH]); };
+      auto right = [&](int yy) { return lnode_of<T>(wk, d, tx0, ty0, e, ty, wk.bidx_v[gR * 2 * T::TH + yy % T::TH]); };
       if (a == b && !(ly > 0 && c == a && dd == b)) lunion(lp, (u32)left(y), (u32)right(y));
       if (ly > 0) {
         if (diag_right_up<T::FG8>(a, b, c, dd)) lunion(lp, (u32)right(y), (u32)left(y - 1));
@@ -1477,6 +1485,7 @@ __global__ void __launch_bounds__(64) k_leaders(Src src, Work wk) {
     bool lead = r != (int)d.node0 && wk.gminkey[r] == wk.gkey[node];
     int rank = (g & 0xFFFF) + (int)pre[i] - (int)pre[first[ly]];
     wk.grank[node] = rank | (ly << 16) | (lead ? (int)HI : 0);
+    if (lead) wk.rcanon[r] = rank;  // the component's rank in its first pixel's cell
   }
   for (int ly = lane; ly < th; ly += 64) {
     if (cnt[ly]) wk.cgrid[d.c0 + (int64_t)(y0 + ly) * d.ntx + tx] += (int)cnt[ly];
@@ -1555,49 +1564,40 @@ __global__ void __launch_bounds__(SCAN_T) k_scan_apply(Src src, Work wk) {
 }
 
 // ---------------------------------------------------------------------------
-// K5: canonical ids and features of components that cross tiles
+// K5: the canonical id of every border node (its component's), and the
+// tables of the components that cross tiles, written by the node holding the
+// component's first pixel.  The id is the scanned base of the (row, tile
+// column) cell of the component's first pixel (the minimum key at the root)
+// plus the component's rank among the components starting in that cell,
+// which k_leaders left at the root.
 
 template <class T, class Src>
-__global__ void __launch_bounds__(64) k_emit_border(Src src, Work wk) {
+__global__ void __launch_bounds__(64) k_border_canon(Src src, Work wk) {
   const int64_t gt = blockIdx.x;
   const ImgDesc& d = src.by_tile(gt);
   if (!src.ok(d)) return;
   const int64_t lt = gt - d.tile0;
-  const int tx = (int)(lt % d.ntx), ty = (int)(lt / d.ntx);
-  const int y0 = ty * T::TH;
   const int64_t nbase = tile_node_base<T>(d, lt);
   const int nb = wk.nbt[gt];
   if (lt == 0 && threadIdx.x == 0) {
-    wk.rcanon[d.node0] = 0;
     if (d.feat) d.feat[0] = wk.gacc[d.node0];
     if (d.parent) d.parent[0] = -1;
     if (d.color) d.color[0] = 0;
   }
   for (int i = threadIdx.x; i < nb; i += 64) {
-    int node = (int)(nbase + i);
-    int g = wk.grank[node];
-    if (!(g & (int)HI)) continue;
-    int ly = (g >> 16) & 63;
-    int canon = wk.cgrid[d.c0 + (int64_t)(y0 + ly) * d.ntx + tx] + (g & 0xFFFF);
-    int r = wk.gpar[node];
-    wk.rcanon[r] = canon;
-    if (d.feat && canon < d.cap) d.feat[canon] = wk.gacc[r];
+    const int node = (int)(nbase + i);
+    const int r = wk.gpar[node];
+    const int g = wk.grank[node];
+    int32_t canon = 0;
+    if (r != (int)d.node0) {
+      const int32_t key = wk.gminkey[r];
+      const int32_t rank = wk.rcanon[r];
+      const int y = key / d.w, x = key - y * d.w;
+      canon = wk.cgrid[d.c0 + (int64_t)y * d.ntx + x / T::TW] + rank;
+    }
+    wk.ncanon[node] = canon;
+    if ((g & (int)HI) && d.feat && canon < d.cap) d.feat[canon] = wk.gacc[r];
   }
-}
-
-// K5b: the canonical id of every border node (its root's), so that K6 reads
-// it in one step.  One thread per node slot.
-
-template <class T, class Src>
-__global__ void __launch_bounds__(256) k_node_canon(Src src, Work wk, int64_t slots) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= slots) return;
-  const int64_t gt = i / T::BCAP;
-  const int k = (int)(i % T::BCAP);
-  const ImgDesc& d = src.by_tile(gt);
-  if (!src.ok(d) || k >= wk.nbt[gt]) return;
-  const int node = (int)(tile_node_base<T>(d, gt - d.tile0) + k);
-  wk.ncanon[node] = wk.rcanon[wk.gpar[node]];
 }
 
 // ---------------------------------------------------------------------------
@@ -1692,9 +1692,12 @@ __global__ void __launch_bounds__(T::NT) k_tile_emit(Src src, Work wk) {
     tsv[k] = i < 3 * T::NW ? ts[i] : 0ull;
   }
   const int32_t rowb = tid < th ? wk.cgrid[d.c0 + (int64_t)(y0 + tid) * d.ntx + tx] : 0;
-  // node of the left neighbour's right column, per row (parents of
-  // components whose first pixel is in column 0)
-  const int lnode = tid < th && tx > 0 ? col_node<T>(wk, d, tx - 1, y0 + tid, true) : -1;
+  // slot of the left neighbour's right-column node, per row (parents of
+  // components whose first pixel is in column 0); the node index is formed
+  // where it is first used, so that no wait for this load precedes the
+  // loads below
+  const bool has_left = tid < th && tx > 0;
+  const u32 lslot = has_left ? (u32)wk.bidx_v[((gt - 1) * 2 + 1) * T::TH + tid] : 0u;
   // also, before the tile's kind is known: the first 2 NT run ordinals and
   // the first NT border nodes (entries past the tile's counts are unused)
   const u32 ord2 = reinterpret_cast<const u32*>(wk.tord + gt * T::N)[tid < T::N / 2 ? tid : 0];
@@ -1709,7 +1712,7 @@ __global__ void __launch_bounds__(T::NT) k_tile_emit(Src src, Work wk) {
     if (tid == 0 && (grank0 & (int)HI)) {  // the component starts here
       if (canon < d.cap) {
         if (d.color) d.color[canon] = (u8)col;
-        if (d.parent) d.parent[canon] = tx > 0 ? wk.ncanon[col_node<T>(wk, d, tx - 1, y0, true)] : 0;
+        if (d.parent) d.parent[canon] = tx > 0 ? wk.ncanon[nbase - T::BCAP + lslot] : 0;
       }
       if (d.counts)
         atomicAdd(reinterpret_cast<unsigned long long*>(&d.counts[1]), (unsigned long long)(int64_t)(col ? 1 : -1));
@@ -1732,7 +1735,8 @@ __global__ void __launch_bounds__(T::NT) k_tile_emit(Src src, Work wk) {
   }
 
   // 1. tile state, root ordinals of the runs, row bases; canonical ids of the
-  // border roots (HI marks the ones holding their component's first pixel)
+  // border roots (HI marks the ones holding their component's first pixel);
+  // the first pass of interior accumulators cleared
   const int nruns = info >> 2;
 #pragma unroll
   for (int k = 0; k < (3 * T::NW + T::NT - 1) / T::NT; k++) {
@@ -1754,30 +1758,30 @@ __global__ void __launch_bounds__(T::NT) k_tile_emit(Src src, Work wk) {
   if (tid < nbt && tid < T::BCAP) s.bcanon[tid] = bcan | (bgr & (int)HI);
   for (int bi = T::NT + tid; bi < nbt; bi += T::NT) s.bcanon[bi] = wk.ncanon[nbase + bi] | (wk.grank[nbase + bi] & (int)HI);
   if (tid == 0) s.euler = 0;
+  for (int i = tid; i < T::CAPI; i += T::NT) acc_init(iacc[i]);
   __syncthreads();
-  // the left neighbour's canonical ids are first used in step 8
-  const int32_t lcv = lnode >= 0 ? wk.ncanon[lnode] : 0;
+  // the left neighbour's canonical ids are first used in step 6
+  const int32_t lcv = has_left ? wk.ncanon[nbase - T::BCAP + lslot] : 0;
 
-  // 2. run starts; interior roots lead
-  for (int wd = tid; wd < T::NW; wd += T::NT) {
-    int ly = wd / T::WPR, j = wd % T::WPR;
-    u64 b = s.bits[wd];
-    u64 carry = j ? (s.bits[wd - 1] >> 63) : (~b & 1ull);
-    u64 e = (b ^ ((b << 1) | carry)) & valid_mask(j, tw);
-    s.st[wd] = ly < th ? e : 0ull;
-    s.lmask[wd] = s.rootm[wd] & ~s.broot[wd];
-  }
-  __syncthreads();
-
-  // 3. exclusive prefix counts over words: border roots, interior roots, run starts
+  // 2. one wave, a word per lane: run starts; exclusive prefix counts over
+  // words of border roots, interior roots and run starts; leaders (roots
+  // holding their component's first pixel: every interior root, and the
+  // border roots whose HI mark is set, which is cleared)
   if (tid < 64) {
     u32 cb = 0, ci = 0, cs = 0;
     for (int base = 0; base < T::NW; base += 64) {
-      int wd = base + tid;
-      u64 rm = wd < T::NW ? s.rootm[wd] : 0ull;
-      u64 bm = wd < T::NW ? s.broot[wd] : 0ull;
-      u32 v = (u32)popc64(bm) | ((u32)popc64(rm & ~bm) << 16);
-      u32 vs = wd < T::NW ? (u32)popc64(s.st[wd]) : 0u;
+      const int wd = base + tid;
+      u64 e = 0, rm = 0, bm = 0;
+      if (wd < T::NW) {
+        const int ly = wd / T::WPR, j = wd % T::WPR;
+        const u64 b = s.bits[wd];
+        const u64 carry = j ? (s.bits[wd - 1] >> 63) : (~b & 1ull);
+        e = ly < th ? (b ^ ((b << 1) | carry)) & valid_mask(j, tw) : 0ull;
+        rm = s.rootm[wd];
+        bm = s.broot[wd];
+      }
+      const u32 v = (u32)popc64(bm) | ((u32)popc64(rm & ~bm) << 16);  // both <= 4096 per 64 words
+      const u32 vs = (u32)popc64(e);
       u32 inc = v, incs = vs;
       for (int dl = 1; dl < 64; dl <<= 1) {
         u32 t = __shfl_up(inc, dl, 64);
@@ -1788,12 +1792,24 @@ __global__ void __launch_bounds__(T::NT) k_tile_emit(Src src, Work wk) {
         }
       }
       if (wd < T::NW) {
-        u32 exc = inc - v;
-        s.bpre[wd] = (u16)(cb + (exc & 0xFFFFu));
+        const u32 exc = inc - v;
+        const int bp = (int)(cb + (exc & 0xFFFFu));
+        s.bpre[wd] = (u16)bp;
         s.ipre[wd] = (u16)(ci + (exc >> 16));
         s.spre[wd] = (u16)(cs + incs - vs);
+        s.st[wd] = e;
+        u64 lead = rm & ~bm;
+        int bi = bp;
+        for (u64 m = bm; m; m &= m - 1, bi++) {
+          const int32_t cv = s.bcanon[bi];
+          if (cv & (int32_t)HI) {
+            lead |= m & (~m + 1ull);
+            s.bcanon[bi] = cv & ~(int32_t)HI;
+          }
+        }
+        s.lmask[wd] = lead;
       }
-      u32 tot = __shfl(inc, 63, 64);
+      const u32 tot = __shfl(inc, 63, 64);
       cb += tot & 0xFFFFu;
       ci += tot >> 16;
       cs += __shfl(incs, 63, 64);
@@ -1806,71 +1822,66 @@ __global__ void __launch_bounds__(T::NT) k_tile_emit(Src src, Work wk) {
   }
   __syncthreads();
 
-  // 4. border roots holding their component's first pixel join the leaders
-  for (int c = tid; c < T::NCH; c += T::NT) {
-    int ly = c / T::CPR, cc = c % T::CPR;
-    int j = cc >> 2, sh = (cc & 3) * 16;
-    int wd = ly * T::WPR + j;
-    const u64 bmw = s.broot[wd];
-    u32 lead = 0;
-    for (u32 m = (u32)(bmw >> sh) & 0xFFFFu; m; m &= m - 1) {
-      int k = ctz32(m);
-      int bi = s.bpre[wd] + popc64(bmw & low_mask(sh + k));
-      int32_t cv = s.bcanon[bi];
-      if (cv & (int32_t)HI) {
-        lead |= 1u << k;
-        s.bcanon[bi] = cv & ~(int32_t)HI;
-      }
-    }
-    if (lead) reinterpret_cast<u16*>(s.lmask)[c] |= (u16)lead;
-  }
-  __syncthreads();
-
-  // 5. canonical ids of interior roots (row base + rank among the row's
-  // leaders); Euler number over the components that start here
+  // 3. per chunk: canonical ids of interior roots (row base + rank among the
+  // row's leaders), the Euler number over the components that start here,
+  // and the features of interior components (first CAPI of them)
   const int nb = s.nb;
-  int e_local = 0;
-  for (int c = tid; c < T::NCH; c += T::NT) {
-    int ly = c / T::CPR, cc = c % T::CPR;
-    int j = cc >> 2, sh = (cc & 3) * 16;
-    int wd = ly * T::WPR + j;
-    u32 lm = reinterpret_cast<const u16*>(s.lmask)[c];
-    u32 b16 = reinterpret_cast<const u16*>(s.bits)[c];
-    e_local += popc64(lm & b16) - popc64(lm & ~b16 & 0xFFFFu);
-    const u64 imw = s.rootm[wd] & ~s.broot[wd];
-    u32 im = (u32)(imw >> sh) & 0xFFFFu;
-    if (!im) continue;
-    int rowlead = popc64(s.lmask[wd] & low_mask(sh));
-    for (int jj = 0; jj < j; jj++) rowlead += popc64(s.lmask[ly * T::WPR + jj]);
-    for (; im; im &= im - 1) {
-      int k = ctz32(im);
-      int ii = s.ipre[wd] + popc64(imw & low_mask(sh + k));
-      s.rt.o.icanon[ii] = (u16)((ly << 8) | (rowlead + popc64(lm & ((1u << k) - 1u))));
-    }
-  }
-  e_local = wave_sum(e_local);
-  if ((tid & 63) == 0 && e_local) atomicAdd(&s.euler, e_local);
-  __syncthreads();
-  if (tid == 0 && s.euler != 0 && d.counts)
-    atomicAdd(reinterpret_cast<unsigned long long*>(&d.counts[1]), (unsigned long long)(int64_t)s.euler);
-
-  // 6. features of interior components, CAPI at a time; their colour / parent
   const int nint = s.nint;
-  for (int k0 = 0; k0 < nint; k0 += T::CAPI) {
-    for (int i = tid; i < T::CAPI; i += T::NT) acc_init(iacc[i]);
-    __syncthreads();
+  {
+    int e_local = 0;
     for (int c = tid; c < T::NCH; c += T::NT) {
-      int ly = c / T::CPR, cc = c % T::CPR;
+      const int ly = c / T::CPR, cc = c % T::CPR;
+      const int j = cc >> 2, sh = (cc & 3) * 16;
+      const int wd = ly * T::WPR + j;
+      const u32 lm = reinterpret_cast<const u16*>(s.lmask)[c];
+      const u32 b16 = reinterpret_cast<const u16*>(s.bits)[c];
+      e_local += popc64(lm & b16) - popc64(lm & ~b16 & 0xFFFFu);
+      const u64 imw = s.rootm[wd] & ~s.broot[wd];
+      u32 im = (u32)(imw >> sh) & 0xFFFFu;
+      if (im) {
+        int rowlead = popc64(s.lmask[wd] & low_mask(sh));
+        for (int jj = 0; jj < j; jj++) rowlead += popc64(s.lmask[ly * T::WPR + jj]);
+        for (; im; im &= im - 1) {
+          const int k = ctz32(im);
+          const int ii = s.ipre[wd] + popc64(imw & low_mask(sh + k));
+          s.rt.o.icanon[ii] = (u16)((ly << 8) | (rowlead + popc64(lm & ((1u << k) - 1u))));
+        }
+      }
       if (ly >= th) continue;
       RowSum rs;
       rs.o = -1;
       for_runs<T>(s, ly, cc, tw, [&](int rank, int a, int b) {
-        int o = (int)s.rt.o.ordr[rank] - nb - k0;
+        const int o = (int)s.rt.o.ordr[rank] - nb;
         if (o >= 0 && o < T::CAPI) rowsum_add(rs, iacc, o, ly, a, b);
       });
       rowsum_flush(rs, iacc, ly);
     }
-    __syncthreads();
+    e_local = wave_sum(e_local);
+    if ((tid & 63) == 0 && e_local) atomicAdd(&s.euler, e_local);
+  }
+  __syncthreads();
+  if (tid == 0 && s.euler != 0 && d.counts)
+    atomicAdd(reinterpret_cast<unsigned long long*>(&d.counts[1]), (unsigned long long)(int64_t)s.euler);
+
+  // 4. tables of interior components (colour, parent, features), CAPI at a
+  // time: the first pass was accumulated in step 3
+  for (int k0 = 0; k0 < nint; k0 += T::CAPI) {
+    if (k0 > 0) {
+      for (int i = tid; i < T::CAPI; i += T::NT) acc_init(iacc[i]);
+      __syncthreads();
+      for (int c = tid; c < T::NCH; c += T::NT) {
+        int ly = c / T::CPR, cc = c % T::CPR;
+        if (ly >= th) continue;
+        RowSum rs;
+        rs.o = -1;
+        for_runs<T>(s, ly, cc, tw, [&](int rank, int a, int b) {
+          int o = (int)s.rt.o.ordr[rank] - nb - k0;
+          if (o >= 0 && o < T::CAPI) rowsum_add(rs, iacc, o, ly, a, b);
+        });
+        rowsum_flush(rs, iacc, ly);
+      }
+      __syncthreads();
+    }
     for (int c = tid; c < T::NCH; c += T::NT) {
       int ly = c / T::CPR, cc = c % T::CPR;
       int j = cc >> 2, sh = (cc & 3) * 16;
@@ -1888,12 +1899,12 @@ __global__ void __launch_bounds__(T::NT) k_tile_emit(Src src, Work wk) {
         if (d.parent) d.parent[canon] = canon_of(s, s.rt.o.ordr[run_rank(s, ly, j * 64 + k - 1)]);  // interior: x > 0
       }
     }
-    __syncthreads();
+    if (k0 + T::CAPI < nint) __syncthreads();  // the accumulators are cleared next
   }
 
-  // 7. canonical id of every run, in place of the ordinals (values pass
+  // 5. canonical id of every run, in place of the ordinals (values pass
   // through registers: the two tables overlap); only the label image needs
-  // them, without it the ordinals stay and step 8 maps the few it needs
+  // them, without it the ordinals stay and step 6 maps the few it needs
   const bool lab = d.labels != nullptr;
   if (lab) {
     constexpr int RPT = (T::N + T::NT - 1) / T::NT;
@@ -1915,7 +1926,7 @@ __global__ void __launch_bounds__(T::NT) k_tile_emit(Src src, Work wk) {
   if (tid < th) s.lcanon[tid] = lcv;
   __syncthreads();
 
-  // 8. colour / parent of border components whose first pixel is here
+  // 6. colour / parent of border components whose first pixel is here
   for (int c = tid; c < T::NCH; c += T::NT) {
     int ly = c / T::CPR, cc = c % T::CPR;
     int j = cc >> 2, sh = (cc & 3) * 16;
@@ -1937,7 +1948,7 @@ __global__ void __launch_bounds__(T::NT) k_tile_emit(Src src, Work wk) {
     }
   }
 
-  // 9. label image, four pixels per thread
+  // 7. label image, four pixels per thread
   if (d.labels) {
     const bool vec = (d.flags & DF_VEC_LAB) != 0;
     for (int q = tid; q < T::TH * (T::TW / 4); q += T::NT) {
@@ -1970,7 +1981,7 @@ __global__ void __launch_bounds__(T::NT) k_tile_emit(Src src, Work wk) {
 struct Layout {
   int64_t tiles, nodes, cells, blocks;
   size_t off_gpar, off_gkey, off_gminkey, off_grank, off_rcanon, off_ncanon, off_gacc, off_nbt;
-  size_t off_btop, off_bbot, off_bleft, off_bright, off_bitstop, off_bitsbot, off_bitslr;
+  size_t off_bidxh, off_bidxv, off_bitsh, off_bitslr;
   size_t off_cgrid, off_bsum, off_tinfo, off_tstate, off_tord, bytes;
 };
 
@@ -1997,12 +2008,9 @@ inline Layout make_layout(int64_t tiles, int64_t nodes, int64_t cells, int64_t b
   L.off_ncanon = take(4 * (size_t)nodes);
   L.off_gacc = take(sizeof(Feature) * (size_t)nodes);
   L.off_nbt = take(4 * (size_t)tiles);
-  L.off_btop = take(2 * (size_t)tiles * T::TW);
-  L.off_bbot = take(2 * (size_t)tiles * T::TW);
-  L.off_bleft = take(2 * (size_t)tiles * T::TH);
-  L.off_bright = take(2 * (size_t)tiles * T::TH);
-  L.off_bitstop = take(8 * (size_t)tiles * T::WPR);
-  L.off_bitsbot = take(8 * (size_t)tiles * T::WPR);
+  L.off_bidxh = take(2 * 2 * (size_t)tiles * T::TW);
+  L.off_bidxv = take(2 * 2 * (size_t)tiles * T::TH);
+  L.off_bitsh = take(8 * 2 * (size_t)tiles * T::WPR);
   L.off_bitslr = take(16 * (size_t)tiles);
   L.off_cgrid = take(4 * (size_t)cells);
   L.off_bsum = take(4 * (size_t)blocks);
@@ -2024,12 +2032,9 @@ inline Work make_work(const Layout& L, void* ws) {
   w.ncanon = reinterpret_cast<int32_t*>(b + L.off_ncanon);
   w.gacc = reinterpret_cast<Feature*>(b + L.off_gacc);
   w.nbt = reinterpret_cast<int32_t*>(b + L.off_nbt);
-  w.bidx_top = reinterpret_cast<u16*>(b + L.off_btop);
-  w.bidx_bot = reinterpret_cast<u16*>(b + L.off_bbot);
-  w.bidx_left = reinterpret_cast<u16*>(b + L.off_bleft);
-  w.bidx_right = reinterpret_cast<u16*>(b + L.off_bright);
-  w.bits_top = reinterpret_cast<u64*>(b + L.off_bitstop);
-  w.bits_bot = reinterpret_cast<u64*>(b + L.off_bitsbot);
+  w.bidx_h = reinterpret_cast<u16*>(b + L.off_bidxh);
+  w.bidx_v = reinterpret_cast<u16*>(b + L.off_bidxv);
+  w.bits_h = reinterpret_cast<u64*>(b + L.off_bitsh);
   w.bits_lr = reinterpret_cast<u64*>(b + L.off_bitslr);
   w.cgrid = reinterpret_cast<int32_t*>(b + L.off_cgrid);
   w.bsum = reinterpret_cast<int32_t*>(b + L.off_bsum);
@@ -2078,8 +2083,7 @@ inline void enqueue(Launcher& L, const Src& src, const Work& wk, int64_t tiles, 
   L.launch(k_leaders<T, Src>, tiles, 64, src, wk);
   L.launch(k_scan_reduce<Src>, blocks, SCAN_T, src, wk);
   L.launch(k_scan_apply<Src>, blocks, SCAN_T, src, wk);
-  L.launch(k_emit_border<T, Src>, tiles, 64, src, wk);
-  L.launch(k_node_canon<T, Src>, (tiles * T::BCAP + 255) / 256, 256, src, wk, tiles * T::BCAP);
+  L.launch(k_border_canon<T, Src>, tiles, 64, src, wk);
   // The relabeling of tiles of 8192 pixels or more runs with 512 threads
   // whatever the other kernels use: it is bound by memory latency and its
   // LDS (not wave slots) limits the workgroups per CU, so wider workgroups

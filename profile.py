@@ -28,7 +28,7 @@ import sys
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 KERNELS = ["k_tile_export", "k_seam_local", "k_border_merge", "k_reduce_roots", "k_leaders", "k_scan_reduce",
-           "k_scan_apply", "k_emit_border", "k_node_canon", "k_tile_emit", "k_fill_top", "k_fill_scan", "k_fill_ids",
+           "k_scan_apply", "k_border_canon", "k_tile_emit", "k_fill_top", "k_fill_scan", "k_fill_ids",
            "k_fill_merge", "k_fill_labels"]
 PASSES = {
     "pmc1": ["SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR",
@@ -146,8 +146,10 @@ def summary(workload: str, outdir: str, copydir: str, md: str):
     lines += ["(OUTDIR is made absolute before the runs.)", "", f"Copy calibration ({COPY_MIB} MiB device-to-device): FETCH_SIZE reads {fetch_kib:.0f} KiB "
               f"(scale {f_scale:.3f}), WRITE_SIZE reads {write_kib:.0f} KiB (scale {w_scale:.3f}).", "",
               "Per dispatch averages (every dispatch of the profiled run: warm-up and timed steps):", "",
-              "| kernel | dispatches | avg us | HBM read MB | HBM write MB | VALU/wave | LDS/wave | wait % | LDS bank-conflict % | LDS atomics/wave | L2 atomics/launch |",
-              "|---|---|---|---|---|---|---|---|---|---|---|"]
+              "VALU issue % = VALU instructions x 4 cycles (a wave64 instruction on a 16-lane SIMD) / "
+              "(1024 SIMDs x kernel duration x 2.4 GHz): how busy the vector units are on average.", "",
+              "| kernel | dispatches | avg us | HBM read MB | HBM write MB | VALU/wave | SALU/wave | LDS/wave | VALU issue % | wait % | LDS bank-conflict % | LDS atomics/wave | L2 atomics/launch |",
+              "|---|---|---|---|---|---|---|---|---|---|---|---|---|"]
     traffic = {}
     for k in KERNELS:
         if k not in dur and k not in cnt:
@@ -158,8 +160,11 @@ def summary(workload: str, outdir: str, copydir: str, md: str):
         wr = avg(k, "WRITE_SIZE") * 1024 * w_scale
         traffic[k] = {"read_bytes": int(rd), "write_bytes": int(wr), "bytes_per_launch": int(rd + wr),
                       "avg_us": round(sum(d) / len(d), 2)}
-        lines.append(f"| {k} | {len(d)} | {sum(d) / len(d):.1f} | {rd / 1e6:.1f} | {wr / 1e6:.1f} | "
-                     f"{avg(k, 'SQ_INSTS_VALU') / waves:.0f} | {avg(k, 'SQ_INSTS_LDS') / waves:.0f} | "
+        us = sum(d) / len(d)
+        valu_util = 100 * avg(k, "SQ_INSTS_VALU") * 4 / (1024 * us * 1e-6 * 2.4e9)
+        lines.append(f"| {k} | {len(d)} | {us:.1f} | {rd / 1e6:.1f} | {wr / 1e6:.1f} | "
+                     f"{avg(k, 'SQ_INSTS_VALU') / waves:.0f} | {avg(k, 'SQ_INSTS_SALU') / waves:.0f} | "
+                     f"{avg(k, 'SQ_INSTS_LDS') / waves:.0f} | {valu_util:.0f} | "
                      f"{100 * avg(k, 'SQ_WAIT_ANY') / avg(k, 'SQ_WAVE_CYCLES'):.0f} | "
                      f"{100 * avg(k, 'SQ_LDS_BANK_CONFLICT') / max(avg(k, 'SQ_LDS_IDX_ACTIVE'), 1):.0f} | "
                      f"{avg(k, 'SQ_INSTS_LDS_ATOMIC') / waves:.1f} | {avg(k, 'TCC_ATOMIC_sum'):.0f} |")

@@ -37,7 +37,7 @@ def build(force: bool = False) -> str:
     newest = max(os.path.getmtime(p) for p in (SRC, MOCK, PIPE))
     if force or not os.path.exists(EXE) or os.path.getmtime(EXE) < newest:
         os.makedirs(BUILD, exist_ok=True)
-        tmp = EXE + ".tmp"
+        tmp = f"{EXE}.tmp{os.getpid()}"  # parallel test workers may build at once
         subprocess.check_call([
             CXX, "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer",
             "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
