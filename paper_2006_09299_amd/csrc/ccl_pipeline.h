@@ -407,7 +407,7 @@ struct TileSmem {
   u64 rootm[T::NW];  // roots (position p with par[p] == p at a run start)
   // union-find over positions ly * TW + x (only run starts are used); once
   // the roots are known, the root ordinal of every run start
-  alignas(8) u16 par[T::N];
+  alignas(16) u16 par[T::N];
   u16 bpre[T::NW];   // border roots before word (tile raster order)
   u16 ipre[T::NW];   // interior roots before word
   u16 spre[T::NW];   // run starts before word
@@ -548,8 +548,27 @@ __device__ int tile_pack(TileSmem<T>& s, const TileFetch<T>& f, const ImgDesc& d
       e = (m ^ ((m << 1) | carry)) & vm;
       all0 = all0 && (m & vm) == 0;
       all1 = all1 && (m & vm) == vm;
-      const u32 p0 = (u32)(ly * T::TW + cx);
-      for (u32 t = e; t; t &= t - 1) s.par[swz(p0 + (u32)ctz32(t))] = (u16)(p0 + (u32)ctz32(t));
+    }
+    // par[p] = p for the chunk's 16 positions (only run starts are ever
+    // read): two 16-byte stores instead of a loop over the run starts, whose
+    // count varies from lane to lane.  The chunk fills one aligned block of
+    // 16 entries, which swz permutes: slot i holds position p0 + (i ^ 2 sw).
+    {
+      const u32 p0 = (u32)c * 16u;  // = ly * TW + cx
+      const u32 sw = (p0 >> 7) & 7u;
+      const u32 base = p0 | ((p0 + 1u) << 16);
+      uint4 lo, hi;
+      lo.x = base + ((0u ^ sw) * 2u) * 0x10001u;
+      lo.y = base + ((1u ^ sw) * 2u) * 0x10001u;
+      lo.z = base + ((2u ^ sw) * 2u) * 0x10001u;
+      lo.w = base + ((3u ^ sw) * 2u) * 0x10001u;
+      hi.x = base + ((4u ^ sw) * 2u) * 0x10001u;
+      hi.y = base + ((5u ^ sw) * 2u) * 0x10001u;
+      hi.z = base + ((6u ^ sw) * 2u) * 0x10001u;
+      hi.w = base + ((7u ^ sw) * 2u) * 0x10001u;
+      uint4* dst = reinterpret_cast<uint4*>(&s.par[p0]);
+      dst[0] = lo;
+      dst[1] = hi;
     }
     reinterpret_cast<u16*>(s.st)[c] = (u16)e;
   }
