@@ -141,6 +141,11 @@ struct Work {
 };
 
 constexpr u32 HI = 0x80000000u;
+// Each image's node block starts with its exterior node followed by EXT_REP
+// accumulators of the exterior's features: the root reduction spreads the
+// exterior's partial sums over them by workgroup (one address taking the
+// atomics of every workgroup serialises them), and k_border_canon adds them up.
+constexpr int EXT_REP = 32;
 constexpr int SCAN_T = 256;             // threads of the scan kernels
 constexpr int SCAN_B = SCAN_T * 4;      // entries per scan block
 
@@ -835,7 +840,7 @@ struct ManyImages {
 
 template <class T>
 __device__ inline int64_t tile_node_base(const ImgDesc& d, int64_t lt) {  // slot 0 of local tile lt
-  return d.node0 + 1 + lt * T::BCAP;
+  return d.node0 + 1 + EXT_REP + lt * T::BCAP;
 }
 
 // ---------------------------------------------------------------------------
@@ -850,15 +855,17 @@ __device__ void export_tile(TileSmem<T>& s, Acc* bacc, const ImgDesc& d, const T
   const int x0 = g.x0, y0 = g.y0, tw = g.tw, th = g.th;
   const int tid = threadIdx.x;
 
-  if (lt == 0 && tid == 0) {  // per-image state read by later kernels
-    wk.gpar[d.node0] = (int32_t)d.node0;
-    wk.gminkey[d.node0] = -1;
-    wk.gkey[d.node0] = -1;
+  if (lt == 0 && tid <= EXT_REP) {  // per-image state read by later kernels
     Feature e;
     e.xmin = 0x7FFFFFFF; e.xmax = -1; e.ymin = 0x7FFFFFFF; e.ymax = -1;
     e.S = 0; e.Sx = 0; e.Sy = 0;
-    wk.gacc[d.node0] = e;
-    if (d.counts) d.counts[1] = 0;
+    wk.gacc[d.node0 + tid] = e;  // the exterior and its accumulators
+    if (tid == 0) {
+      wk.gpar[d.node0] = (int32_t)d.node0;
+      wk.gminkey[d.node0] = -1;
+      wk.gkey[d.node0] = -1;
+      if (d.counts) d.counts[1] = 0;
+    }
   }
 
   const int64_t nbase = tile_node_base<T>(d, lt);
@@ -1344,6 +1351,7 @@ __global__ void __launch_bounds__(RH_T) k_reduce_roots(Src src, Work wk, int64_t
   __shared__ RootAcc tab[RH_CAP];
   __shared__ int pre[RHT + 1];
   __shared__ int64_t tbase[RHT];
+  __shared__ int32_t text[RHT];  // exterior node of the tile's image
   __shared__ int used;
   const int tid = threadIdx.x;
   const int64_t t0 = (int64_t)blockIdx.x * RHT;
@@ -1356,6 +1364,7 @@ __global__ void __launch_bounds__(RH_T) k_reduce_roots(Src src, Work wk, int64_t
       const ImgDesc& d = src.by_tile(gt);
       c = src.ok(d) ? wk.nbt[gt] : 0;
       tbase[tid] = tile_node_base<T>(d, gt - d.tile0);
+      text[tid] = (int32_t)d.node0;
     }
     int inc = c;
     for (int dl = 1; dl < 64; dl <<= 1) {
@@ -1411,8 +1420,22 @@ __global__ void __launch_bounds__(RH_T) k_reduce_roots(Src src, Work wk, int64_t
         RootAcc& a = tab[j];
         if (a.key == RH_EMPTY) continue;
         int r = a.key;
-        atomicMin(&wk.gminkey[r], a.minkey);
-        Feature* g = &wk.gacc[r];
+        // an exterior is the first node of its image's block, before all
+        // of its tiles' nodes: compare with the one of the last tile whose
+        // exterior is at or before r (no minimum key: the exterior's id is 0)
+        int lo = 0, hi = ntl - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (text[mid] <= r) lo = mid;
+          else hi = mid - 1;
+        }
+        Feature* g;
+        if (text[lo] == r) {
+          g = &wk.gacc[r + 1 + (int)(blockIdx.x % EXT_REP)];
+        } else {
+          atomicMin(&wk.gminkey[r], a.minkey);
+          g = &wk.gacc[r];
+        }
         atomicMin(&g->xmin, a.xmin);
         atomicMax(&g->xmax, a.xmax);
         atomicMin(&g->ymin, a.ymin);
@@ -1442,9 +1465,14 @@ __global__ void __launch_bounds__(64) k_reduce_direct(Src src, Work wk) {
     int node = (int)(nbase + i);
     int r = gfind(wk.gpar, node);  // leaves gpar[node] == r
     if (r == node) continue;
-    atomicMin(&wk.gminkey[r], wk.gkey[node]);
+    Feature* g;
+    if (r == (int)d.node0) {  // the exterior: one of its accumulators
+      g = &wk.gacc[r + 1 + (int)(gt % EXT_REP)];
+    } else {
+      atomicMin(&wk.gminkey[r], wk.gkey[node]);
+      g = &wk.gacc[r];
+    }
     Feature f = wk.gacc[node];
-    Feature* g = &wk.gacc[r];
     atomicMin(&g->xmin, f.xmin);
     atomicMax(&g->xmax, f.xmax);
     atomicMin(&g->ymin, f.ymin);
@@ -1599,7 +1627,20 @@ __global__ void __launch_bounds__(64) k_border_canon(Src src, Work wk) {
   const int64_t nbase = tile_node_base<T>(d, lt);
   const int nb = wk.nbt[gt];
   if (lt == 0 && threadIdx.x == 0) {
-    if (d.feat) d.feat[0] = wk.gacc[d.node0];
+    if (d.feat) {
+      Feature e = wk.gacc[d.node0];
+      for (int k = 1; k <= EXT_REP; k++) {
+        const Feature f = wk.gacc[d.node0 + k];
+        e.xmin = f.xmin < e.xmin ? f.xmin : e.xmin;
+        e.xmax = f.xmax > e.xmax ? f.xmax : e.xmax;
+        e.ymin = f.ymin < e.ymin ? f.ymin : e.ymin;
+        e.ymax = f.ymax > e.ymax ? f.ymax : e.ymax;
+        e.S += f.S;
+        e.Sx += f.Sx;
+        e.Sy += f.Sy;
+      }
+      d.feat[0] = e;
+    }
     if (d.parent) d.parent[0] = -1;
     if (d.color) d.color[0] = 0;
   }
@@ -2081,7 +2122,7 @@ inline void place_image(ImgDesc& d, int64_t& tiles, int64_t& nodes, int64_t& cel
   d.s0 = supers;
   supers += (int64_t)((d.ntx + T::SUP - 1) / T::SUP) * ((d.nty + T::SUP - 1) / T::SUP);
   tiles += nt;
-  nodes += 1 + nt * T::BCAP;
+  nodes += 1 + EXT_REP + nt * T::BCAP;
   cells += nc;
   blocks += d.nblk;
   items += d.nit;
