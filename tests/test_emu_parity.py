@@ -51,8 +51,11 @@ def test_emulated_kernels_batched_padded_pitch():
 def test_emulated_kernels_production_tile():
     # the dense 128 x 2048 image fills the root-reduction hash of a tile group
     # more than once (flush while scanning, then at the end)
+    block = np.zeros((100, 300), np.uint8)
+    block[10:90, 20:280] = 1  # whole one-colour tiles inside, ragged ones around
     imgs = _cases(11, 4, 80, 400) + [synth.bernoulli_blocks(70, 300, 0.5, 1, 5),
-                                     synth.bernoulli_blocks(128, 2048, 0.5, 1, 3)]
+                                     synth.bernoulli_blocks(128, 2048, 0.5, 1, 3),
+                                     np.ones((64, 256), np.uint8), block]
     for img, r in zip(imgs, emu_runner.run(imgs, tile_cfg=0, pitch_pad=16)):
         _assert_same(img, r)
 
