@@ -95,7 +95,7 @@ def test_emulated_kernels_complementary_connectivity(cfg):
 def test_emulated_features_only(cfg, batch):
     """No label image (labels = NULL): every table equal to the oracle's, and
     the label buffer left untouched."""
-    imgs = _cases(400 + cfg, 6, 40, 300) + [synth.bernoulli_blocks(128, 512, 0.5, 1, 8)]
+    imgs = _cases(400 + cfg, 3, 40, 300) + [synth.bernoulli_blocks(64 if cfg == 1 else 128, 512, 0.5, 1, 8)]
     fg8 = cfg != 8
     for img, r in zip(imgs, emu_runner.run(imgs, tile_cfg=cfg, batch=batch, labels=False)):
         o = oracle.label(img, fg8=fg8)
@@ -112,9 +112,11 @@ def test_emulated_merge_schedules(cfg):
     """Super-tiles of 2 x 2 and 8 x 8 tiles (the seams k_seam_local merges in
     LDS against those left to k_border_merge move) and root-reduction groups
     of 4 and 1 tiles, single and batched."""
-    imgs = _cases(500 + cfg, 8, 60, 700)
+    # 4 x 64 tiles: a 40 x 400 image spans 10 x 7 tiles, so 2 x 2 and 8 x 8
+    # super-tiles and their seams both occur
+    imgs = _cases(500 + cfg, 3, 48, 520)
     for img, r in zip(imgs, emu_runner.run(imgs, tile_cfg=cfg)):
         _assert_same(img, r)
-    imgs = _cases(600 + cfg, 6, 50, 400)
+    imgs = _cases(600 + cfg, 3, 36, 300)
     for img, r in zip(imgs, emu_runner.run(imgs, tile_cfg=cfg, batch=True, pitch_pad=7)):
         _assert_same(img, r)
