@@ -1,7 +1,16 @@
 """Plant plausible mistakes in copies of the oracle source (on the CPU) and
-check that the pins in this suite catch every one of them."""
+check that the pins in this suite catch every one of them.
+
+Each mutant runs in a child process: a planted mistake may also write out of
+bounds (a renumbering that skips an id indexes past the tables), which must
+not corrupt the memory of the test process itself.  A child that crashes has
+not passed the pins either."""
 import os
 import subprocess
+import sys
+
+if __name__ == "__main__":  # child process: the repository root for the oracle package
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 
 import numpy as np
 import pytest
@@ -66,5 +75,12 @@ def test_mutant_is_caught(name, tmp_path):
     mpath.write_text(src.replace(old, new, 1))
     so = tmp_path / "libmutant.so"
     subprocess.check_call(["gcc", "-O1", "-std=c99", "-shared", "-fPIC", str(mpath), "-o", str(so)])
-    lib = oracle.load_variant(str(so))
-    assert not _pins_hold(lib), f"mutant {name} survived the pins"
+    child = subprocess.run([sys.executable, os.path.abspath(__file__), str(so)], capture_output=True, text=True,
+                           timeout=300)
+    assert child.returncode != 0 or "PINS HOLD" not in child.stdout, f"mutant {name} survived the pins"
+    if child.returncode == 0:
+        assert "PINS FAIL" in child.stdout, child.stdout + child.stderr
+
+
+if __name__ == "__main__":  # child: the pins on one build of the oracle source
+    print("PINS HOLD" if _pins_hold(oracle.load_variant(sys.argv[1])) else "PINS FAIL", flush=True)
