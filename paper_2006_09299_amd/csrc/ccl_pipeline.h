@@ -63,6 +63,7 @@
 #pragma once
 
 #include <stdint.h>
+#include <type_traits>
 
 namespace ccl {
 
@@ -2176,13 +2177,14 @@ inline uint32_t scatter_stride(int64_t tiles) {
 template <class T, bool HASH, class Src, class Launcher>
 inline void enqueue(Launcher& L, const Src& src, const Work& wk0, int64_t tiles, int64_t items, int64_t blocks,
                     int64_t supers) {
-  // K1 takes its tiles in a scattered order: neighbouring tiles tend to be of
-  // one kind (one-colour tiles, which only load, or general tiles, which
-  // compute), and workgroups of both kinds resident together overlap better
-  // than a run of either (measured: -12 % on K1 for the structured 16384^2
-  // images, no change on random ones; K6 gains nothing and keeps raster order).
+  // K1 takes the tiles of a single image in a scattered order: neighbouring
+  // tiles tend to be of one kind (one-colour tiles, which only load, or
+  // general tiles, which compute), and workgroups of both kinds resident
+  // together overlap better than a run of either (measured: -12 % on K1 for
+  // the structured 16384^2 images, no change on random ones; K6 gains
+  // nothing; a batch of small images loses 2 % and keeps raster order).
   Work wk = wk0;
-  wk.k1_stride = scatter_stride(tiles);
+  if constexpr (std::is_same<Src, OneImage>::value) wk.k1_stride = scatter_stride(tiles);
   L.launch(k_tile_export<T, Src>, tiles, T::NT, src, wk);
   L.launch(k_seam_local<T, Src>, supers, SL_T, src, wk);
   if (items > 0) L.launch(k_border_merge<T, Src>, (items + 255) / 256, 256, src, wk, items);
