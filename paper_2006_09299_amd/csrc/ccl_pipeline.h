@@ -1965,22 +1965,39 @@ __global__ void __launch_bounds__(T::NT) k_tile_emit(Src src, Work wk) {
       }
       __syncthreads();
     }
-    for (int c = tid; c < T::NCH; c += T::NT) {
-      int ly = c / T::CPR, cc = c % T::CPR;
-      int j = cc >> 2, sh = (cc & 3) * 16;
-      int wd = ly * T::WPR + j;
-      const u64 imw = s.rootm[wd] & ~s.broot[wd];
-      for (u32 im = (u32)(imw >> sh) & 0xFFFFu; im; im &= im - 1) {
-        int k = sh + ctz32(im);
-        int ii = s.ipre[wd] + popc64(imw & low_mask(k));
-        int o = ii - k0;
-        if (o < 0 || o >= T::CAPI) continue;
-        int32_t canon = canon_of(s, nb + ii);
-        if (canon >= d.cap) continue;
-        if (d.feat) d.feat[canon] = acc_abs(iacc[o], ly, x0, y0);
-        if (d.color) d.color[canon] = (u8)((s.bits[wd] >> k) & 1ull);
-        if (d.parent) d.parent[canon] = canon_of(s, s.rt.o.ordr[run_rank(s, ly, j * 64 + k - 1)]);  // interior: x > 0
+    // one thread per interior component (not one per chunk: a chunk's
+    // components would be worked off one after another by its lane)
+    const int kn = nint - k0 < T::CAPI ? nint - k0 : T::CAPI;
+    for (int o = tid; o < kn; o += T::NT) {
+      const int ii = k0 + o;
+      // the word holding the ii-th interior root: the first whose inclusive
+      // count exceeds ii (ipre is the exclusive count)
+      int lo = 0, hi = T::NW - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        const int incl = mid + 1 < T::NW ? (int)s.ipre[mid + 1] : nint;
+        if (incl > ii) hi = mid;
+        else lo = mid + 1;
       }
+      const int wd = lo;
+      // its bit: the (ii - ipre)-th set bit of the word's interior roots
+      u64 m = s.rootm[wd] & ~s.broot[wd];
+      int r = ii - (int)s.ipre[wd], k = 0;
+#pragma unroll
+      for (int half = 32; half >= 1; half >>= 1) {
+        const int c = popc64(m & low_mask(half));
+        if (r >= c) {
+          r -= c;
+          m >>= half;
+          k += half;
+        }
+      }
+      const int ly = wd / T::WPR, xk = (wd % T::WPR) * 64 + k;
+      const int32_t canon = canon_of(s, nb + ii);
+      if (canon >= d.cap) continue;
+      if (d.feat) d.feat[canon] = acc_abs(iacc[o], ly, x0, y0);
+      if (d.color) d.color[canon] = (u8)((s.bits[wd] >> (xk & 63)) & 1ull);
+      if (d.parent) d.parent[canon] = canon_of(s, s.rt.o.ordr[run_rank(s, ly, xk - 1)]);  // interior: x > 0
     }
     if (k0 + T::CAPI < nint) __syncthreads();  // the accumulators are cleared next
   }
