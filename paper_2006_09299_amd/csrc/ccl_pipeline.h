@@ -139,6 +139,7 @@ struct Work {
   u64* tstate;       // [tiles*3*NW] foreground bits, root masks, border-root masks
   u16* tord;         // [tiles*N] root ordinal of every run, by run rank
                      // (border roots first, then interior roots, raster order)
+  int32_t* rcol;     // [tiles*TH] canonical id of the component at each row's last pixel
   uint32_t k1_stride;  // K1's tile order: block b labels tile (b * k1_stride) mod tiles
 };
 
@@ -1642,12 +1643,15 @@ __global__ void __launch_bounds__(SCAN_T) k_scan_apply(Src src, Work wk) {
 
 template <class T, class Src>
 __global__ void __launch_bounds__(64) k_border_canon(Src src, Work wk) {
+  __shared__ int32_t cl[T::BCAP];  // canonical id by node slot
   const int64_t gt = blockIdx.x;
   const ImgDesc& d = src.by_tile(gt);
   if (!src.ok(d)) return;
   const int64_t lt = gt - d.tile0;
   const int64_t nbase = tile_node_base<T>(d, lt);
   const int nb = wk.nbt[gt];
+  // node slot of each row's last pixel (entries past the tile's rows unused)
+  const u16 rslot = wk.bidx_v[(gt * 2 + 1) * T::TH + (threadIdx.x < T::TH ? threadIdx.x : 0)];
   if (lt == 0 && threadIdx.x == 0) {
     if (d.feat) {
       Feature e = wk.gacc[d.node0];
@@ -1678,8 +1682,15 @@ __global__ void __launch_bounds__(64) k_border_canon(Src src, Work wk) {
       canon = wk.cgrid[d.c0 + (int64_t)y * d.ntx + x / T::TW] + rank;
     }
     wk.ncanon[node] = canon;
+    cl[i] = canon;
     if ((g & (int)HI) && d.feat && canon < d.cap) d.feat[canon] = wk.gacc[r];
   }
+  // the ids at the right column, row by row: the parents of the components
+  // of the right neighbour whose first pixel is in its column 0
+  __syncthreads();
+  const int y0 = (int)(lt / d.ntx) * T::TH;
+  const int th = d.h - y0 < T::TH ? d.h - y0 : T::TH;
+  if ((int)threadIdx.x < th) wk.rcol[gt * T::TH + threadIdx.x] = cl[rslot];
 }
 
 // ---------------------------------------------------------------------------
@@ -1776,7 +1787,7 @@ __global__ void __launch_bounds__(T::NT) k_tile_emit(Src src, Work wk) {
     if (tid == 0 && (grank0 & (int)HI)) {  // the component starts here
       if (canon < d.cap) {
         if (d.color) d.color[canon] = (u8)col;
-        if (d.parent) d.parent[canon] = tx > 0 ? wk.ncanon[nbase - T::BCAP + wk.bidx_v[((gt - 1) * 2 + 1) * T::TH]] : 0;
+        if (d.parent) d.parent[canon] = tx > 0 ? wk.rcol[(gt - 1) * T::TH] : 0;
       }
       if (d.counts)
         atomicAdd(reinterpret_cast<unsigned long long*>(&d.counts[1]), (unsigned long long)(int64_t)(col ? 1 : -1));
@@ -1810,12 +1821,11 @@ __global__ void __launch_bounds__(T::NT) k_tile_emit(Src src, Work wk) {
     tsv[k] = i < 3 * T::NW ? ts[i] : 0ull;
   }
   const int32_t rowb = tid < th ? wk.cgrid[d.c0 + (int64_t)(y0 + tid) * d.ntx + tx] : 0;
-  // slot of the left neighbour's right-column node, per row (parents of
-  // components whose first pixel is in column 0), read from any row (and
-  // this tile's own entries at the image's left edge, not used then) so
-  // that the read is not conditional: its first use is after the barrier
+  // canonical id at the left neighbour's right column, per row (parents of
+  // components whose first pixel is in column 0; 0, the exterior, at the
+  // image's left edge)
   const bool has_left = tid < th && tx > 0;
-  const u16 lraw = wk.bidx_v[((tx > 0 ? gt - 1 : gt) * 2 + 1) * T::TH + (tid < th ? tid : 0)];
+  const int32_t lcv = has_left ? wk.rcol[(gt - 1) * T::TH + tid] : 0;
   const u32 ord2 = reinterpret_cast<const u32*>(wk.tord + gt * T::N)[tid < T::N / 2 ? tid : 0];
   const int bslot = tid < T::BCAP ? tid : 0;
   const int32_t bcan = wk.ncanon[nbase + bslot];
@@ -1843,8 +1853,6 @@ __global__ void __launch_bounds__(T::NT) k_tile_emit(Src src, Work wk) {
   if (tid == 0) s.euler = 0;
   for (int i = tid; i < T::CAPI; i += T::NT) acc_init(iacc[i]);
   __syncthreads();
-  // the left neighbour's canonical ids are first used in step 6
-  const int32_t lcv = has_left ? wk.ncanon[nbase - T::BCAP + lraw] : 0;
 
   // 2. one wave, a word per lane: run starts; exclusive prefix counts over
   // words of border roots, interior roots and run starts; leaders (roots
@@ -2082,7 +2090,7 @@ struct Layout {
   int64_t tiles, nodes, cells, blocks;
   size_t off_gpar, off_gkey, off_gminkey, off_grank, off_rcanon, off_ncanon, off_gacc, off_nbt;
   size_t off_bidxh, off_bidxv, off_bitsh, off_bitslr;
-  size_t off_cgrid, off_bsum, off_tinfo, off_tstate, off_tord, bytes;
+  size_t off_cgrid, off_bsum, off_tinfo, off_tstate, off_tord, off_rcol, bytes;
 };
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -2117,6 +2125,7 @@ inline Layout make_layout(int64_t tiles, int64_t nodes, int64_t cells, int64_t b
   L.off_tinfo = take(4 * (size_t)tiles);
   L.off_tstate = take(8 * 3 * (size_t)tiles * T::NW);
   L.off_tord = take(2 * (size_t)tiles * T::N);
+  L.off_rcol = take(4 * (size_t)tiles * T::TH);
   L.bytes = o;
   return L;
 }
@@ -2141,6 +2150,7 @@ inline Work make_work(const Layout& L, void* ws) {
   w.tinfo = reinterpret_cast<int32_t*>(b + L.off_tinfo);
   w.tstate = reinterpret_cast<u64*>(b + L.off_tstate);
   w.tord = reinterpret_cast<u16*>(b + L.off_tord);
+  w.rcol = reinterpret_cast<int32_t*>(b + L.off_rcol);
   w.k1_stride = 1u;
   return w;
 }
