@@ -1714,7 +1714,7 @@ struct EmitSmem {
     } o;
     int32_t rcan[T::N];  // finally: canonical id by run rank
   } rt;
-  int32_t bcanon[T::BCAP];  // canonical id of border root ordinal o (o < nb)
+  int32_t bcanon[T::BCAP];  // canonical id of border root ordinal o (o < nb); HI: holds its first pixel
   int32_t rowbase[T::TH];  // first canonical id of the row's components starting here
   int32_t lcanon[T::TH];   // canonical id of the pixel left of the tile, per row
   int nb, nint, nruns, euler;
@@ -1726,7 +1726,7 @@ __device__ inline int32_t canon_of(const EmitSmem<T>& s, int o) {
   // both tables are read (no divergent branch), the right one selected
   const int nb = s.nb;
   const bool border = o < nb;
-  const int32_t cb = s.bcanon[border ? o : 0];
+  const int32_t cb = s.bcanon[border ? o : 0] & ~(int32_t)HI;
   const u32 v = s.rt.o.icanon[border ? 0 : o - nb];
   const int32_t ci = s.rowbase[v >> 8] + (int32_t)(v & 0xFFu);
   return border ? cb : ci;
@@ -1854,30 +1854,50 @@ __global__ void __launch_bounds__(T::NT) k_tile_emit(Src src, Work wk) {
   for (int i = tid; i < T::CAPI; i += T::NT) acc_init(iacc[i]);
   __syncthreads();
 
-  // 2. one wave, a word per lane: run starts; exclusive prefix counts over
-  // words of border roots, interior roots and run starts; leaders (roots
-  // holding their component's first pixel: every interior root, and the
-  // border roots whose HI mark is set, which is cleared)
-  if (tid < 64) {
-    u32 cb = 0, ci = 0, cs = 0;
-    for (int base = 0; base < T::NW; base += 64) {
-      const int wd = base + tid;
-      u64 e = 0, rm = 0, bm = 0;
-      if (wd < T::NW) {
-        const int ly = wd / T::WPR, j = wd % T::WPR;
-        const u64 b = s.bits[wd];
-        const u64 carry = j ? (s.bits[wd - 1] >> 63) : (~b & 1ull);
-        e = ly < th ? (b ^ ((b << 1) | carry)) & valid_mask(j, tw) : 0ull;
-        rm = s.rootm[wd];
-        bm = s.broot[wd];
+  // 2. a word per lane, one wave per 64 words: run starts; exclusive prefix
+  // counts over words of border roots, interior roots and run starts
+  // (each wave adds the counts of the words before its own, which it sums
+  // itself: no wave waits for another); leaders (roots holding their
+  // component's first pixel: every interior root, and the border roots
+  // whose HI mark is set)
+  {
+    constexpr int NWV = (T::NW + 63) / 64;  // waves at work
+    static_assert(NWV * 64 <= T::NT, "a wave per 64 words");
+    const int wv = tid >> 6, lane = tid & 63;
+    // the counts of one word: border roots | interior roots << 16, run starts
+    auto counts = [&](int wd, u64& e, u64& rm, u64& bm) {
+      const int ly = wd / T::WPR, j = wd % T::WPR;
+      const u64 b = s.bits[wd];
+      const u64 carry = j ? (s.bits[wd - 1] >> 63) : (~b & 1ull);
+      e = ly < th ? (b ^ ((b << 1) | carry)) & valid_mask(j, tw) : 0ull;
+      rm = s.rootm[wd];
+      bm = s.broot[wd];
+    };
+    if (wv < NWV) {
+      // counts of the words before this wave's
+      u32 cb = 0, ci = 0, cs = 0;
+      for (int wd = lane; wd < 64 * wv; wd += 64) {
+        u64 e, rm, bm;
+        counts(wd, e, rm, bm);
+        cb += (u32)popc64(bm);
+        ci += (u32)popc64(rm & ~bm);
+        cs += (u32)popc64(e);
       }
+      if (wv > 0) {
+        cb = (u32)wave_sum((int)cb);
+        ci = (u32)wave_sum((int)ci);
+        cs = (u32)wave_sum((int)cs);
+      }
+      const int wd = 64 * wv + lane;
+      u64 e = 0, rm = 0, bm = 0;
+      if (wd < T::NW) counts(wd, e, rm, bm);
       const u32 v = (u32)popc64(bm) | ((u32)popc64(rm & ~bm) << 16);  // both <= 4096 per 64 words
       const u32 vs = (u32)popc64(e);
       u32 inc = v, incs = vs;
       for (int dl = 1; dl < 64; dl <<= 1) {
         u32 t = __shfl_up(inc, dl, 64);
         u32 t2 = __shfl_up(incs, dl, 64);
-        if (tid >= dl) {
+        if (lane >= dl) {
           inc += t;
           incs += t2;
         }
@@ -1890,25 +1910,19 @@ __global__ void __launch_bounds__(T::NT) k_tile_emit(Src src, Work wk) {
         s.spre[wd] = (u16)(cs + incs - vs);
         s.st[wd] = e;
         u64 lead = rm & ~bm;
+        // (reads only: the mark stays in the table and is masked where the
+        // ids are read, so that the reads of a word's roots overlap)
         int bi = bp;
         for (u64 m = bm; m; m &= m - 1, bi++) {
-          const int32_t cv = s.bcanon[bi];
-          if (cv & (int32_t)HI) {
-            lead |= m & (~m + 1ull);
-            s.bcanon[bi] = cv & ~(int32_t)HI;
-          }
+          if (s.bcanon[bi] & (int32_t)HI) lead |= m & (~m + 1ull);
         }
         s.lmask[wd] = lead;
       }
-      const u32 tot = __shfl(inc, 63, 64);
-      cb += tot & 0xFFFFu;
-      ci += tot >> 16;
-      cs += __shfl(incs, 63, 64);
-    }
-    if (tid == 0) {
-      s.nb = (int)cb;
-      s.nint = (int)ci;
-      s.nruns = (int)cs;
+      if (wv == NWV - 1 && lane == 63) {
+        s.nb = (int)(cb + (inc & 0xFFFFu));
+        s.nint = (int)(ci + (inc >> 16));
+        s.nruns = (int)(cs + incs);
+      }
     }
   }
   __syncthreads();
@@ -2042,7 +2056,7 @@ __global__ void __launch_bounds__(T::NT) k_tile_emit(Src src, Work wk) {
     const u64 bmw = s.broot[wd];
     for (u32 bl = (u32)((bmw & s.lmask[wd]) >> sh) & 0xFFFFu; bl; bl &= bl - 1) {
       int k = sh + ctz32(bl);
-      int32_t canon = s.bcanon[s.bpre[wd] + popc64(bmw & low_mask(k))];
+      int32_t canon = s.bcanon[s.bpre[wd] + popc64(bmw & low_mask(k))] & ~(int32_t)HI;
       if (canon >= d.cap) continue;
       if (d.color) d.color[canon] = (u8)((s.bits[wd] >> k) & 1ull);
       if (d.parent) {
