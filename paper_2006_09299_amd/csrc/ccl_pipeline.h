@@ -404,10 +404,18 @@ __device__ inline bool diag_left_up(int a, int b, int c, int dd) {  // (left, y)
 }
 
 // packed per-component accumulators: S | Sx << 16 | Sy << 40 (tile-local
-// coordinates), bounding box extremes; ymin is the row of the first pixel
+// coordinates), bounding box extremes; ymin is the row of the first pixel.
+// Acc (K1's border partials) keeps each extreme in a word of its own; AccP
+// (K6's interior components) both x extremes in one word, so that the
+// record takes 16 bytes and K6's LDS leaves room for four workgroups per CU.
 struct Acc {
   u64 s;
   u32 xmin, xmax, ymax;
+};
+struct AccP {
+  u64 s;
+  u32 xr;  // xmin | xmax << 16
+  u32 ymax;
 };
 
 __device__ inline u64 seg_pack(int ly, int s, int e) {
@@ -778,6 +786,11 @@ __device__ inline void acc_init(Acc& a) {
   a.xmax = 0;
   a.ymax = 0;
 }
+__device__ inline void acc_init(AccP& a) {
+  a.s = 0;
+  a.xr = 0xFFFFu;  // xmin 0xFFFF, xmax 0
+  a.ymax = 0;
+}
 // Segments of one row summed in registers before they go to a shared
 // accumulator: consecutive segments (in x order) of one component.
 struct RowSum {
@@ -785,19 +798,36 @@ struct RowSum {
   u64 s;       // packed S | Sx | Sy
   u32 xmin, xmax;
 };
-__device__ inline void rowsum_flush(RowSum& r, Acc* acc, int ly) {
+// the extremes only ever move outwards: an atomic is needed only when the
+// value read does not already include this one (reads of one address by
+// many lanes are served at once, atomics on it one after another)
+__device__ inline void acc_x(Acc& a, u32 xmin, u32 xmax) {
+  if (xmin < ld_wg(&a.xmin)) atomicMin(&a.xmin, xmin);
+  if (xmax > ld_wg(&a.xmax)) atomicMax(&a.xmax, xmax);
+}
+__device__ inline void acc_x(AccP& a, u32 xmin, u32 xmax) {
+  // both in one word: merged by compare-and-swap, which succeeds or returns
+  // a value that already moved one of them outwards
+  u32 old = ld_wg(&a.xr);
+  while (xmin < (old & 0xFFFFu) || xmax > (old >> 16)) {
+    const u32 lo = xmin < (old & 0xFFFFu) ? xmin : (old & 0xFFFFu);
+    const u32 hi = xmax > (old >> 16) ? xmax : (old >> 16);
+    const u32 prev = atomicCAS(&a.xr, old, lo | (hi << 16));
+    if (prev == old) break;
+    old = prev;
+  }
+}
+template <class A>
+__device__ inline void rowsum_flush(RowSum& r, A* acc, int ly) {
   if (r.o < 0) return;
-  Acc& a = acc[r.o];
+  A& a = acc[r.o];
   atomicAdd(&a.s, r.s);
-  // the extremes only ever move outwards: an atomic is needed only when the
-  // value read does not already include this one (reads of one address by
-  // many lanes are served at once, atomics on it one after another)
-  if (r.xmin < ld_wg(&a.xmin)) atomicMin(&a.xmin, r.xmin);
-  if (r.xmax > ld_wg(&a.xmax)) atomicMax(&a.xmax, r.xmax);
+  acc_x(a, r.xmin, r.xmax);
   if ((u32)ly > ld_wg(&a.ymax)) atomicMax(&a.ymax, (u32)ly);
   r.o = -1;
 }
-__device__ inline void rowsum_add(RowSum& r, Acc* acc, int o, int ly, int s0, int e0) {
+template <class A>
+__device__ inline void rowsum_add(RowSum& r, A* acc, int o, int ly, int s0, int e0) {
   if (o != r.o) {
     rowsum_flush(r, acc, ly);
     r.o = o;
@@ -808,13 +838,18 @@ __device__ inline void rowsum_add(RowSum& r, Acc* acc, int o, int ly, int s0, in
   r.xmax = (u32)(e0 - 1);
 }
 
-__device__ inline Feature acc_abs(const Acc& a, int ly_min, int x0, int y0) {
+__device__ inline u32 acc_xmin(const Acc& a) { return a.xmin; }
+__device__ inline u32 acc_xmax(const Acc& a) { return a.xmax; }
+__device__ inline u32 acc_xmin(const AccP& a) { return a.xr & 0xFFFFu; }
+__device__ inline u32 acc_xmax(const AccP& a) { return a.xr >> 16; }
+template <class A>
+__device__ inline Feature acc_abs(const A& a, int ly_min, int x0, int y0) {
   Feature f;
   int64_t S = (int64_t)(a.s & 0xFFFFull);
   int64_t sx = (int64_t)((a.s >> 16) & 0xFFFFFFull);
   int64_t sy = (int64_t)(a.s >> 40);
-  f.xmin = (int32_t)a.xmin + x0;
-  f.xmax = (int32_t)a.xmax + x0;
+  f.xmin = (int32_t)acc_xmin(a) + x0;
+  f.xmax = (int32_t)acc_xmax(a) + x0;
   f.ymin = ly_min + y0;
   f.ymax = (int32_t)a.ymax + y0;
   f.S = S;
@@ -1707,12 +1742,18 @@ struct EmitSmem {
   u16 spre[T::NW];     // run starts before word (tile raster order)
   u16 bpre[T::NW];     // border roots before word
   u16 ipre[T::NW];     // interior roots before word
-  union {
-    struct {
-      u16 ordr[T::N];    // root ordinal by run rank
-      u16 icanon[T::N];  // interior root nb + i: row << 8 | rank among the row's leaders
-    } o;
-    int32_t rcan[T::N];  // finally: canonical id by run rank
+  struct {
+    u16 ordr[T::N];  // root ordinal by run rank
+    // interior root nb + i: row << 8 | rank among the row's leaders.  A
+    // tile has fewer than N / 2 interior components: their first pixels
+    // (the roots) lie off the tile's edge rows and columns, and no two are
+    // next to each other in a row (if (x, y) and (x + 1, y) both were
+    // first pixels, (x + 1, y - 1) has the colour of (x, y), else it would
+    // precede (x + 1, y) in its component; if that colour is the
+    // 8-adjacent one it joins (x, y) from an earlier row, else (x, y - 1)
+    // has the other colour, which then joins (x + 1, y) diagonally from an
+    // earlier row)
+    u16 icanon[T::N / 2];
   } rt;
   int32_t bcanon[T::BCAP];  // canonical id of border root ordinal o (o < nb); HI: holds its first pixel
   int32_t rowbase[T::TH];  // first canonical id of the row's components starting here
@@ -1727,7 +1768,7 @@ __device__ inline int32_t canon_of(const EmitSmem<T>& s, int o) {
   const int nb = s.nb;
   const bool border = o < nb;
   const int32_t cb = s.bcanon[border ? o : 0] & ~(int32_t)HI;
-  const u32 v = s.rt.o.icanon[border ? 0 : o - nb];
+  const u32 v = s.rt.icanon[border ? 0 : o - nb];
   const int32_t ci = s.rowbase[v >> 8] + (int32_t)(v & 0xFFu);
   return border ? cb : ci;
 }
@@ -1761,7 +1802,7 @@ __device__ inline void for_runs(const EmitSmem<T>& s, int ly, int cc, int tw, Fn
 template <class T, class Src>
 __global__ void __launch_bounds__(T::NT) k_tile_emit(Src src, Work wk) {
   __shared__ EmitSmem<T> s;
-  __shared__ Acc iacc[T::CAPI];
+  __shared__ AccP iacc[T::CAPI];
   const int64_t gt = blockIdx.x;
   const ImgDesc& d = src.by_tile(gt);
   if (!src.ok(d)) return;
@@ -1843,10 +1884,10 @@ __global__ void __launch_bounds__(T::NT) k_tile_emit(Src src, Work wk) {
   }
   const u16* to = wk.tord + gt * T::N;
   if (2 * tid < nruns && tid < T::N / 2) {
-    s.rt.o.ordr[2 * tid] = (u16)(ord2 & 0xFFFFu);
-    if (2 * tid + 1 < nruns) s.rt.o.ordr[2 * tid + 1] = (u16)(ord2 >> 16);
+    s.rt.ordr[2 * tid] = (u16)(ord2 & 0xFFFFu);
+    if (2 * tid + 1 < nruns) s.rt.ordr[2 * tid + 1] = (u16)(ord2 >> 16);
   }
-  for (int r = 2 * T::NT + tid; r < nruns; r += T::NT) s.rt.o.ordr[r] = to[r];
+  for (int r = 2 * T::NT + tid; r < nruns; r += T::NT) s.rt.ordr[r] = to[r];
   if (tid < th) s.rowbase[tid] = rowb;
   if (tid < nbt && tid < T::BCAP) s.bcanon[tid] = bcan | (bgr & (int)HI);
   for (int bi = T::NT + tid; bi < nbt; bi += T::NT) s.bcanon[bi] = wk.ncanon[nbase + bi] | (wk.grank[nbase + bi] & (int)HI);
@@ -1949,14 +1990,14 @@ __global__ void __launch_bounds__(T::NT) k_tile_emit(Src src, Work wk) {
         for (; im; im &= im - 1) {
           const int k = ctz32(im);
           const int ii = s.ipre[wd] + popc64(imw & low_mask(sh + k));
-          s.rt.o.icanon[ii] = (u16)((ly << 8) | (rowlead + popc64(lm & ((1u << k) - 1u))));
+          if (ii < T::N / 2) s.rt.icanon[ii] = (u16)((ly << 8) | (rowlead + popc64(lm & ((1u << k) - 1u))));
         }
       }
       if (ly >= th) continue;
       RowSum rs;
       rs.o = -1;
       for_runs<T>(s, ly, cc, tw, [&](int rank, int a, int b) {
-        const int o = (int)s.rt.o.ordr[rank] - nb;
+        const int o = (int)s.rt.ordr[rank] - nb;
         if (o >= 0 && o < T::CAPI) rowsum_add(rs, iacc, o, ly, a, b);
       });
       rowsum_flush(rs, iacc, ly);
@@ -1980,7 +2021,7 @@ __global__ void __launch_bounds__(T::NT) k_tile_emit(Src src, Work wk) {
         RowSum rs;
         rs.o = -1;
         for_runs<T>(s, ly, cc, tw, [&](int rank, int a, int b) {
-          int o = (int)s.rt.o.ordr[rank] - nb - k0;
+          int o = (int)s.rt.ordr[rank] - nb - k0;
           if (o >= 0 && o < T::CAPI) rowsum_add(rs, iacc, o, ly, a, b);
         });
         rowsum_flush(rs, iacc, ly);
@@ -2019,32 +2060,12 @@ __global__ void __launch_bounds__(T::NT) k_tile_emit(Src src, Work wk) {
       if (canon >= d.cap) continue;
       if (d.feat) d.feat[canon] = acc_abs(iacc[o], ly, x0, y0);
       if (d.color) d.color[canon] = (u8)((s.bits[wd] >> (xk & 63)) & 1ull);
-      if (d.parent) d.parent[canon] = canon_of(s, s.rt.o.ordr[run_rank(s, ly, xk - 1)]);  // interior: x > 0
+      if (d.parent) d.parent[canon] = canon_of(s, s.rt.ordr[run_rank(s, ly, xk - 1)]);  // interior: x > 0
     }
     if (k0 + T::CAPI < nint) __syncthreads();  // the accumulators are cleared next
   }
 
-  // 5. canonical id of every run, in place of the ordinals (values pass
-  // through registers: the two tables overlap); only the label image needs
-  // them, without it the ordinals stay and step 6 maps the few it needs
-  const bool lab = d.labels != nullptr;
-  if (lab) {
-    constexpr int RPT = (T::N + T::NT - 1) / T::NT;
-    int32_t rc[RPT];
-#pragma unroll
-    for (int k = 0; k < RPT; k++) {
-      const int r = tid + k * T::NT;
-      if (r >= nruns) break;
-      rc[k] = canon_of(s, s.rt.o.ordr[r]);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < RPT; k++) {
-      const int r = tid + k * T::NT;
-      if (r >= nruns) break;
-      s.rt.rcan[r] = rc[k];
-    }
-  }
+  // 5. the left neighbour's ids where step 6 reads them
   if (tid < th) s.lcanon[tid] = lcv;
   __syncthreads();
 
@@ -2063,14 +2084,14 @@ __global__ void __launch_bounds__(T::NT) k_tile_emit(Src src, Work wk) {
         int x = j * 64 + k;
         int32_t pc;
         if (x == 0) pc = s.lcanon[ly];  // 0 (exterior) at the image's left edge
-        else if (lab) pc = s.rt.rcan[run_rank(s, ly, x - 1)];
-        else pc = canon_of(s, s.rt.o.ordr[run_rank(s, ly, x - 1)]);
+        else pc = canon_of(s, s.rt.ordr[run_rank(s, ly, x - 1)]);
         d.parent[canon] = pc;
       }
     }
   }
 
-  // 7. label image, four pixels per thread
+  // 7. label image, four pixels per thread (the canonical id of each run
+  // the four pixels touch, taken from the root ordinal once per run)
   if (d.labels) {
     const bool vec = (d.flags & DF_VEC_LAB) != 0;
     for (int q = tid; q < T::TH * (T::TW / 4); q += T::NT) {
@@ -2082,10 +2103,10 @@ __global__ void __launch_bounds__(T::NT) k_tile_emit(Src src, Work wk) {
       const int r2 = r1 + (int)((sw >> 2) & 1u);
       const int r3 = r2 + (int)((sw >> 3) & 1u);
       int32_t lab[4];
-      lab[0] = s.rt.rcan[r0];
-      lab[1] = s.rt.rcan[r1];
-      lab[2] = s.rt.rcan[r2];
-      lab[3] = s.rt.rcan[r3];
+      lab[0] = canon_of(s, s.rt.ordr[r0]);
+      lab[1] = r1 == r0 ? lab[0] : canon_of(s, s.rt.ordr[r1]);
+      lab[2] = r2 == r1 ? lab[1] : canon_of(s, s.rt.ordr[r2]);
+      lab[3] = r3 == r2 ? lab[2] : canon_of(s, s.rt.ordr[r3]);
       int32_t* dst = d.labels + (int64_t)(y0 + ly) * d.w + x0 + x;
       if (vec && x + 4 <= tw) {
         store_labels4(dst, lab[0], lab[1], lab[2], lab[3]);

@@ -60,11 +60,14 @@ def test_emulated_kernels_production_tile():
         _assert_same(img, r)
 
 
-def test_emulated_many_interior_components_per_tile():
+@pytest.mark.parametrize("cfg", [0, 7, 8])
+def test_emulated_many_interior_components_per_tile(cfg):
     # a checkerboard puts one hole on every second pixel: more interior
-    # components in a 32 x 128 tile than one accumulator pass holds
-    img = ((np.add.outer(np.arange(40), np.arange(200)) % 2) == 0).astype(np.uint8)
-    _assert_same(img, emu_runner.run([img], tile_cfg=0)[0])
+    # components in a tile than one accumulator pass holds, and close to the
+    # bound on their number (half the tile); 8: the complementary pair, where
+    # the foreground pixels are the singletons
+    img = ((np.add.outer(np.arange(70), np.arange(140)) % 2) == 0).astype(np.uint8)
+    _assert_same(img, emu_runner.run([img], tile_cfg=cfg)[0], fg8=cfg != 8)
 
 
 @pytest.mark.parametrize("sched", ["rev", "12345"])
