@@ -1127,14 +1127,14 @@ __device__ inline int col_bit(const Work& wk, const ImgDesc& d, int tcol, int y,
 
 template <class T>
 __host__ __device__ inline int64_t merge_items(int w, int h, int ntx, int nty) {
-  // horizontal seams on super-tile row edges (every 16-pixel quarter of
-  // every word), horizontal seams inside super-tiles (the two edge words of
+  // horizontal seams on super-tile row edges (every 4 pixels of every
+  // word), horizontal seams inside super-tiles (the two edge words of
   // each super-tile column), vertical seams on super-tile column edges
   // (every row), exterior (top / bottom rows by quarter words, left / right
   // columns by row)
   const int64_t nwr = (w + 63) / 64, nstx = (ntx + T::SUP - 1) / T::SUP;
   const int64_t hb = (nty - 1) / T::SUP, hi = (nty - 1) - hb, vb = (ntx - 1) / T::SUP;
-  return hb * nwr * 4 + hi * 2 * nstx + vb * h + 8 * nwr + 2 * (int64_t)h;
+  return hb * nwr * 16 + hi * 2 * nstx + vb * h + 8 * nwr + 2 * (int64_t)h;
 }
 
 // ---------------------------------------------------------------------------
@@ -1258,24 +1258,26 @@ __global__ void __launch_bounds__(256) k_border_merge(Src src, Work wk, int64_t 
   constexpr int SW = T::SUP * T::WPR;  // words per super-tile column
   const int nstx = (d.ntx + T::SUP - 1) / T::SUP;
   const int64_t hb = (d.nty - 1) / T::SUP, hi = (d.nty - 1) - hb, vb = (d.ntx - 1) / T::SUP;
-  const int64_t nH = hb * nwr * 4 + hi * 2 * nstx;
+  const int64_t nH = hb * nwr * 16 + hi * 2 * nstx;
   const int64_t nV = vb * d.h;
   if (i < nH) {  // horizontal seam: bottom row of tile row e-1 above top row of tile row e
     int e, jw;
     bool inner;
     u64 part = ~0ull;  // the word's bits this item unites
-    if (i < hb * nwr * 4) {  // on a super-tile row edge: one 16-pixel quarter
-                             // of a word per item (a dense row has up to 32
-                             // union points per word, each a chain of finds)
-      const int64_t iw = i >> 2;
+    if (i < hb * nwr * 16) {  // on a super-tile row edge: 4 pixels of a word
+                              // per item (a dense row has up to 32 union
+                              // points per word, each a chain of finds: a
+                              // quarter word per item was 13 % slower on
+                              // random images, a whole word 2.4 times)
+      const int64_t iw = i >> 4;
       e = T::SUP * (int)(iw / nwr + 1);
       jw = (int)(iw % nwr);
-      part = 0xFFFFull << (16 * (int)(i & 3));
+      part = 0xFull << (4 * (int)(i & 15));
       inner = false;
     } else {  // inside super-tiles, merged by k_seam_local except for the
               // diagonals that leave a super-tile column at its edge words
-      const int64_t q = (i - hb * nwr * 4) / (2 * nstx);
-      const int r = (int)((i - hb * nwr * 4) % (2 * nstx));
+      const int64_t q = (i - hb * nwr * 16) / (2 * nstx);
+      const int r = (int)((i - hb * nwr * 16) % (2 * nstx));
       e = (int)(q + 1 + q / (T::SUP - 1));  // the q-th seam index that is not a multiple of T::SUP
       jw = (r >> 1) * SW + ((r & 1) ? SW - 1 : 0);
       if (jw >= nwr) return;
