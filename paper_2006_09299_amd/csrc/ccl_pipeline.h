@@ -1267,8 +1267,8 @@ __global__ void __launch_bounds__(256) k_border_merge(Src src, Work wk, int64_t 
     if (i < hb * nwr * 16) {  // on a super-tile row edge: 4 pixels of a word
                               // per item (a dense row has up to 32 union
                               // points per word, each a chain of finds: a
-                              // quarter word per item was 13 % slower on
-                              // random images, a whole word 2.4 times)
+                              // quarter word per item was 15 % slower on
+                              // random images, a whole word twice as slow)
       const int64_t iw = i >> 4;
       e = T::SUP * (int)(iw / nwr + 1);
       jw = (int)(iw % nwr);
