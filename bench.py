@@ -545,7 +545,7 @@ def run_widened(work, reps: int = 3):
     h, w = work[0][1].shape
     buf = ccl.Buffers(w, h, w * h // 4 + 1024, dev)
     fo = ccl.Buffers(w, h, w * h // 4 + 1024, dev, labels=False)
-    c4 = ccl.Buffers(w, h, w * h // 4 + 1024, dev)
+    c4 = ccl.Buffers(w, h, w * h // 4 + 1024, dev, variant=0)
     olab = torch.empty((h, w), dtype=torch.int32, device=dev)
     ofeat = torch.empty((buf.cap, 5), dtype=torch.int64, device=dev)
     opar = torch.empty(buf.cap, dtype=torch.int32, device=dev)

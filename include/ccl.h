@@ -79,11 +79,20 @@ typedef struct {
   ccl_outputs_t out;
 } ccl_image_t;
 
-/* [host] Workspace bytes needed by ccl_label for a w x h image (pure). */
+/* [host] Workspace bytes needed by ccl_label for a w x h image (pure; 0 on
+ * bad input). */
 size_t ccl_workspace_bytes(int32_t w, int32_t h);
 
+/* [host] The variant (see below) ccl_label, ccl_label_traced and
+ * ccl_label_noalloc run for a w x h image: 16 x 128 tiles up to 1.5
+ * Mpixel, 32 x 128 tiles up to 6 Mpixel, else 64 x 128 tiles (smaller
+ * images are faster with smaller tiles; results never depend on it).
+ * CCL_EINVAL for w or h <= 0. */
+int32_t ccl_variant_for(int32_t w, int32_t h);
+
 /* Label one image: img[y*pitch + x], y < h, x < w.  Enqueues the whole path
- * on `stream`.  `ws` needs no initialisation; its contents are scratch. */
+ * on `stream`, in the variant ccl_variant_for(w, h) names.  `ws` needs no
+ * initialisation; its contents are scratch. */
 int ccl_label(const uint8_t *img, int32_t w, int32_t h, int64_t pitch, const ccl_outputs_t *out, void *ws,
               size_t ws_bytes, void *stream);
 
@@ -114,8 +123,10 @@ int ccl_label_noalloc(const uint8_t *img, int32_t w, int32_t h, int64_t pitch, c
  * unification algorithm, Sec. 3.2): fg_adjacency = 8 is the default pair
  * (8-adjacent foreground, 4-adjacent background); 4 the complementary one
  * (4-adjacent foreground, 8-adjacent background: components, tree and
- * Euler number E = #foreground components - #holes under that pair).  Same
- * workspace as ccl_label; CCL_EINVAL for any other fg_adjacency. */
+ * Euler number E = #foreground components - #holes under that pair).  It
+ * runs in the 64 x 128 tile shape of variant 0 and needs
+ * ccl_workspace_bytes_v(w, h, 0) of workspace; CCL_EINVAL for any other
+ * fg_adjacency. */
 int ccl_label_conn(const uint8_t *img, int32_t w, int32_t h, int64_t pitch, const ccl_outputs_t *out, void *ws,
                    size_t ws_bytes, void *stream, int32_t fg_adjacency);
 
@@ -140,8 +151,9 @@ const char *ccl_kernel_name(int k);
  * before the seams between them are merged in device memory, and the number
  * of tiles per workgroup of the root reduction).  All variants give
  * identical results; they differ in speed per workload.
- * Variant 0 (64 x 128 tiles, 256 threads, LDS hash) is the default of
- * ccl_label.  For tiles of 8192 pixels or more the relabeling kernel
+ * Variant 0 (64 x 128 tiles, 256 threads, LDS hash) is the default for
+ * large images; ccl_variant_for names the one a single-image call takes.
+ * For tiles of 8192 pixels or more the relabeling kernel
  * (k_tile_emit) always runs 512 threads per tile. */
 
 /* [host] Number of compiled variants. */

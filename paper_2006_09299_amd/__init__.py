@@ -56,15 +56,16 @@ class Result:
 class Buffers:
     """Preallocated outputs + workspace for repeated calls on one image shape."""
 
-    def __init__(self, w: int, h: int, cap: int, device, labels: bool = True, variant: int = 0):
+    def __init__(self, w: int, h: int, cap: int, device, labels: bool = True, variant: Optional[int] = None):
         self.w, self.h, self.cap = int(w), int(h), int(cap)
-        self.variant = int(variant)
+        # None: the variant ccl_label itself runs for this size
+        self.variant = _capi.variant_for(w, h) if variant is None else int(variant)
         self.labels = torch.empty((h, w), dtype=torch.int32, device=device) if labels else None
         self.features = torch.empty((cap, 5), dtype=torch.int64, device=device)
         self.parent = torch.empty(cap, dtype=torch.int32, device=device)
         self.color = torch.empty(cap, dtype=torch.uint8, device=device)
         self.counts = torch.zeros(2, dtype=torch.int64, device=device)
-        self.ws_bytes = workspace_bytes(w, h, variant)
+        self.ws_bytes = workspace_bytes(w, h, self.variant)
         self.ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=device)
         self.out = _capi.ccl_outputs_t(
             self.labels.data_ptr() if labels else None, self.features.data_ptr(), self.parent.data_ptr(),
@@ -87,8 +88,8 @@ def _check_image(img: torch.Tensor):
 
 def launch(img: torch.Tensor, buf: Buffers, stream: Optional[int] = None, fg_adjacency: int = 8) -> None:
     """Enqueue one labeling into preallocated buffers (no synchronisation).
-    fg_adjacency=4 takes the complementary connectivity pair (default variant
-    only)."""
+    fg_adjacency=4 takes the complementary connectivity pair (buffers made
+    for variant 0 only)."""
     w, h, pitch = _check_image(img)
     if (w, h) != (buf.w, buf.h):
         raise ValueError("buffers were made for another shape")
@@ -99,13 +100,14 @@ def launch(img: torch.Tensor, buf: Buffers, stream: Optional[int] = None, fg_adj
                                      buf.ws_bytes, ctypes.c_void_p(stream), buf.variant)
     else:
         if buf.variant != 0:
-            raise ValueError("the complementary connectivity pair is compiled for the default variant only")
+            raise ValueError("the complementary connectivity pair is compiled for variant 0 only "
+                             "(Buffers(..., variant=0))")
         rc = _capi.lib().ccl_label_conn(img.data_ptr(), w, h, pitch, ctypes.byref(buf.out), buf.ws.data_ptr(),
                                         buf.ws_bytes, ctypes.c_void_p(stream), int(fg_adjacency))
     _capi.check(rc, "ccl_label")
 
 
-def label(img: torch.Tensor, cap: Optional[int] = None, labels: bool = True, variant: int = 0,
+def label(img: torch.Tensor, cap: Optional[int] = None, labels: bool = True, variant: Optional[int] = None,
           fg_adjacency: int = 8) -> Result:
     """Label one image; synchronises to read the number of labels.
 
@@ -114,6 +116,8 @@ def label(img: torch.Tensor, cap: Optional[int] = None, labels: bool = True, var
     fg_adjacency: 8 (8-adjacent foreground, 4-adjacent background) or 4 (the
     complementary pair)."""
     w, h, pitch = _check_image(img)
+    if variant is None and fg_adjacency != 8:
+        variant = 0  # the complementary pair is compiled in variant 0's shape
     full = w * h + 1
     if cap is None:
         cap = min(full, max(1024, full // 4))

@@ -70,7 +70,7 @@ EXPORTS = (
     "ccl_variant_info", "ccl_workspace_bytes_v", "ccl_label_v", "ccl_batch_sizes", "ccl_batch_prepare",
     "ccl_label_batch", "ccl_strerror", "ccl_tile_shape", "ccl_server_create", "ccl_server_footprint",
     "ccl_server_submit", "ccl_server_poll", "ccl_server_release", "ccl_server_stats", "ccl_server_destroy",
-    "ccl_fill_workspace_bytes", "ccl_fill_holes", "ccl_label_conn", "ccl_label_noalloc",
+    "ccl_fill_workspace_bytes", "ccl_fill_holes", "ccl_label_conn", "ccl_label_noalloc", "ccl_variant_for",
 )
 NOALLOC_SCRATCH_BYTES = 96 << 20  # CCL_NOALLOC_SCRATCH_BYTES
 TRACE_EVENTS = 10
@@ -94,6 +94,8 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         L.ccl_workspace_bytes.restype = ctypes.c_size_t
         L.ccl_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
+        L.ccl_variant_for.restype = ctypes.c_int32
+        L.ccl_variant_for.argtypes = [ctypes.c_int32, ctypes.c_int32]
         L.ccl_label.restype = ctypes.c_int
         L.ccl_label.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64,
                                 ctypes.POINTER(ccl_outputs_t), ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
@@ -164,8 +166,18 @@ def check(code: int, where: str) -> None:
         raise CclError(code, where)
 
 
-def workspace_bytes(w: int, h: int, variant: int = 0) -> int:
+def workspace_bytes(w: int, h: int, variant=None) -> int:
+    """Workspace of `variant`, or (None) of what ccl_label runs for the size."""
+    if variant is None:
+        return int(lib().ccl_workspace_bytes(int(w), int(h)))
     return int(lib().ccl_workspace_bytes_v(int(w), int(h), int(variant)))
+
+
+def variant_for(w: int, h: int) -> int:
+    """The variant ccl_label runs for a w x h image."""
+    v = int(lib().ccl_variant_for(int(w), int(h)))
+    check(v if v < 0 else 0, "ccl_variant_for")
+    return v
 
 
 def num_variants() -> int:

@@ -34,6 +34,18 @@ def test_strerror_and_tile_shape():
     assert th >= 1 and tw % 64 == 0
 
 
+def test_single_image_variant_by_size():
+    """ccl_label takes smaller tiles for smaller images; its workspace size is
+    that variant's."""
+    L = _capi.lib()
+    for (w, h), v in [((512, 512), 2), ((1024, 1024), 2), ((1300, 1300), 5), ((2048, 2048), 5),
+                      ((2600, 2400), 5), ((4096, 4096), 0), ((16384, 16384), 0), ((1, 1), 2)]:
+        assert _capi.variant_for(w, h) == v, (w, h)
+        assert L.ccl_workspace_bytes(w, h) == L.ccl_workspace_bytes_v(w, h, v) > 0
+        assert _capi.workspace_bytes(w, h) == L.ccl_workspace_bytes(w, h)
+    assert L.ccl_variant_for(0, 5) == _capi.CCL_EINVAL and L.ccl_variant_for(5, -1) == _capi.CCL_EINVAL
+
+
 def test_workspace_bytes_pure_and_monotone():
     a = _capi.workspace_bytes(512, 512)
     assert a > 0 and a == _capi.workspace_bytes(512, 512)
