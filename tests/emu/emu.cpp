@@ -8,8 +8,8 @@
 //            then n_labels x (int64 xmin,xmax,ymin,ymax,S,Sx,Sy; int32 parent; int32 color)
 #include <stdio.h>
 #include <stdlib.h>
+#include <stdint.h>
 #include <string.h>
-#include <ucontext.h>
 
 #include <vector>
 
@@ -22,13 +22,42 @@
 
 #include "../../paper_2006_09299_amd/csrc/ccl_pipeline.h"
 
+// Fiber switch (x86-64 System V): push the callee-saved registers on the
+// current stack, store its pointer in *save, load the other stack's pointer,
+// pop its registers and return into it.  Unlike swapcontext it makes no
+// system call (swapcontext saves and restores the signal mask on every
+// switch, which was most of the harness's run time).
+extern "C" void emu_switch(void** save, void* load);
+asm(R"(
+  .text
+  .globl emu_switch
+  .type emu_switch, @function
+emu_switch:
+  pushq %rbp
+  pushq %rbx
+  pushq %r12
+  pushq %r13
+  pushq %r14
+  pushq %r15
+  movq %rsp, (%rdi)
+  movq %rsi, %rsp
+  popq %r15
+  popq %r14
+  popq %r13
+  popq %r12
+  popq %rbx
+  popq %rbp
+  ret
+  .size emu_switch, .-emu_switch
+)");
+
 namespace {
 
 constexpr size_t STACK = 512 * 1024;
 enum { RUNNABLE, WAITING, DONE };
 
 struct Fiber {
-  ucontext_t ctx;
+  void* sp;  // saved stack pointer while switched out
   unsigned tid;
   int state;
   int wait_scope;  // 0: block, 1 + wave: wave
@@ -36,7 +65,7 @@ struct Fiber {
 };
 
 struct Sched {
-  ucontext_t main_ctx;
+  void* main_sp;
   std::vector<Fiber> f;
   std::vector<char*> stacks;
   unsigned cur = 0;
@@ -62,8 +91,12 @@ void fiber_entry() {
 #if EMU_ASAN
   __sanitizer_start_switch_fiber(nullptr, S.main_stack_bottom, S.main_stack_size);
 #endif
-  swapcontext(&me.ctx, &S.main_ctx);
+  emu_switch(&me.sp, S.main_sp);  // never resumed
+  abort();
 }
+
+// first frame of a fiber (entered by emu_switch's return, as if called)
+extern "C" void emu_fiber_start() { fiber_entry(); }
 
 void yield_to_main() {
   Fiber& me = S.f[S.cur];
@@ -71,7 +104,7 @@ void yield_to_main() {
   void* fake = nullptr;
   __sanitizer_start_switch_fiber(&fake, S.main_stack_bottom, S.main_stack_size);
 #endif
-  swapcontext(&me.ctx, &S.main_ctx);
+  emu_switch(&me.sp, S.main_sp);
 #if EMU_ASAN
   __sanitizer_finish_switch_fiber(fake, &S.main_stack_bottom, &S.main_stack_size);
 #endif
@@ -97,11 +130,14 @@ void run_block(unsigned block, unsigned nthreads) {
     fb.tid = t;
     fb.state = RUNNABLE;
     fb.stack = S.stacks[t];
-    getcontext(&fb.ctx);
-    fb.ctx.uc_stack.ss_sp = fb.stack;
-    fb.ctx.uc_stack.ss_size = STACK;
-    fb.ctx.uc_link = nullptr;
-    makecontext(&fb.ctx, fiber_entry, 0);
+    // initial frame: six zero registers, then emu_fiber_start as the return
+    // address, then a null return address for it (it never returns), with
+    // the stack 16-byte aligned at the call
+    void** p = reinterpret_cast<void**>((reinterpret_cast<uintptr_t>(fb.stack) + STACK) & ~(uintptr_t)15);
+    *--p = nullptr;
+    *--p = reinterpret_cast<void*>(&emu_fiber_start);
+    for (int k = 0; k < 6; k++) *--p = nullptr;
+    fb.sp = p;
   }
   const unsigned nwaves = (nthreads + 63) / 64;
   // order in which runnable fibers run after each barrier release: thread
@@ -129,7 +165,7 @@ void run_block(unsigned block, unsigned nthreads) {
       void* fake = nullptr;
       __sanitizer_start_switch_fiber(&fake, S.f[t].stack, STACK);
 #endif
-      swapcontext(&S.main_ctx, &S.f[t].ctx);
+      emu_switch(&S.main_sp, S.f[t].sp);
 #if EMU_ASAN
       __sanitizer_finish_switch_fiber(fake, nullptr, nullptr);
 #endif

@@ -74,7 +74,7 @@ def test_emulated_many_interior_components_per_tile(cfg):
 def test_emulated_kernels_other_thread_orders(sched):
     # threads that pass a barrier first go on before the others have read the
     # shared state written before it: reverse and shuffled thread orders
-    imgs = _cases(21, 3, 60, 300) + [synth.bernoulli_blocks(128, 2048, 0.5, 1, 3)]
+    imgs = _cases(21, 3, 60, 300) + [synth.bernoulli_blocks(96, 768, 0.5, 1, 3)]
     for img, r in zip(imgs, emu_runner.run(imgs, tile_cfg=0, sched=sched)):
         _assert_same(img, r)
     imgs = _cases(22, 6, 30, 200)
