@@ -1746,8 +1746,9 @@ struct EmitSmem {
   u16 ipre[T::NW];     // interior roots before word
   struct {
     u16 ordr[T::N];  // root ordinal by run rank
-    // interior root nb + i: row << 8 | rank among the row's leaders.  A
-    // tile has fewer than N / 2 interior components: their first pixels
+    // interior root nb + i: its position (row * TW + column), from step 5 on
+    // row << 8 | rank among the row's leaders.  A tile has fewer than N / 2
+    // interior components: their first pixels
     // (the roots) lie off the tile's edge rows and columns, and no two are
     // next to each other in a row (if (x, y) and (x + 1, y) both were
     // first pixels, (x + 1, y - 1) has the colour of (x, y), else it would
@@ -1755,7 +1756,7 @@ struct EmitSmem {
     // 8-adjacent one it joins (x, y) from an earlier row, else (x, y - 1)
     // has the other colour, which then joins (x + 1, y) diagonally from an
     // earlier row)
-    u16 icanon[T::N / 2];
+    u16 ipos[T::N / 2];
   } rt;
   int32_t bcanon[T::BCAP];  // canonical id of border root ordinal o (o < nb); HI: holds its first pixel
   int32_t rowbase[T::TH];  // first canonical id of the row's components starting here
@@ -1763,15 +1764,28 @@ struct EmitSmem {
   int nb, nint, nruns, euler;
 };
 
-// canonical id of root ordinal o
-template <class T>
+// canonical id of root ordinal o; the interior table holds positions
+// (POS) or, once step 5 has converted it, row << 8 | rank among the row's
+// leaders
+template <bool POS, class T>
 __device__ inline int32_t canon_of(const EmitSmem<T>& s, int o) {
   // both tables are read (no divergent branch), the right one selected
   const int nb = s.nb;
   const bool border = o < nb;
   const int32_t cb = s.bcanon[border ? o : 0] & ~(int32_t)HI;
-  const u32 v = s.rt.icanon[border ? 0 : o - nb];
-  const int32_t ci = s.rowbase[v >> 8] + (int32_t)(v & 0xFFu);
+  const u32 v = s.rt.ipos[border ? 0 : o - nb];
+  int32_t ci;
+  if constexpr (POS) {
+    // the row's base plus the leaders before the root in its row
+    const int ly = (int)(v / T::TW), x = (int)(v % T::TW), j = x >> 6;
+    int rank = popc64(s.lmask[ly * T::WPR + j] & low_mask(x & 63));
+#pragma unroll
+    for (int jj = 0; jj < T::WPR - 1; jj++)
+      if (jj < j) rank += popc64(s.lmask[ly * T::WPR + jj]);
+    ci = s.rowbase[ly] + (int32_t)rank;
+  } else {
+    ci = s.rowbase[v >> 8] + (int32_t)(v & 0xFFu);
+  }
   return border ? cb : ci;
 }
 
@@ -1970,9 +1984,9 @@ __global__ void __launch_bounds__(T::NT) k_tile_emit(Src src, Work wk) {
   }
   __syncthreads();
 
-  // 3. per chunk: canonical ids of interior roots (row base + rank among the
-  // row's leaders), the Euler number over the components that start here,
-  // and the features of interior components (first CAPI of them)
+  // 3. per chunk: positions of the interior roots, the Euler number over
+  // the components that start here, and the features of interior components
+  // (first CAPI of them)
   const int nb = s.nb;
   const int nint = s.nint;
   {
@@ -1986,14 +2000,8 @@ __global__ void __launch_bounds__(T::NT) k_tile_emit(Src src, Work wk) {
       e_local += popc64(lm & b16) - popc64(lm & ~b16 & 0xFFFFu);
       const u64 imw = s.rootm[wd] & ~s.broot[wd];
       u32 im = (u32)(imw >> sh) & 0xFFFFu;
-      if (im) {
-        int rowlead = popc64(s.lmask[wd] & low_mask(sh));
-        for (int jj = 0; jj < j; jj++) rowlead += popc64(s.lmask[ly * T::WPR + jj]);
-        for (; im; im &= im - 1) {
-          const int k = ctz32(im);
-          const int ii = s.ipre[wd] + popc64(imw & low_mask(sh + k));
-          if (ii < T::N / 2) s.rt.icanon[ii] = (u16)((ly << 8) | (rowlead + popc64(lm & ((1u << k) - 1u))));
-        }
+      for (int ii = s.ipre[wd] + popc64(imw & low_mask(sh)); im; im &= im - 1, ii++) {
+        if (ii < T::N / 2) s.rt.ipos[ii] = (u16)(ly * T::TW + j * 64 + sh + ctz32(im));
       }
       if (ly >= th) continue;
       RowSum rs;
@@ -2035,39 +2043,31 @@ __global__ void __launch_bounds__(T::NT) k_tile_emit(Src src, Work wk) {
     const int kn = nint - k0 < T::CAPI ? nint - k0 : T::CAPI;
     for (int o = tid; o < kn; o += T::NT) {
       const int ii = k0 + o;
-      // the word holding the ii-th interior root: the first whose inclusive
-      // count exceeds ii (ipre is the exclusive count)
-      int lo = 0, hi = T::NW - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        const int incl = mid + 1 < T::NW ? (int)s.ipre[mid + 1] : nint;
-        if (incl > ii) hi = mid;
-        else lo = mid + 1;
-      }
-      const int wd = lo;
-      // its bit: the (ii - ipre)-th set bit of the word's interior roots
-      u64 m = s.rootm[wd] & ~s.broot[wd];
-      int r = ii - (int)s.ipre[wd], k = 0;
-#pragma unroll
-      for (int half = 32; half >= 1; half >>= 1) {
-        const int c = popc64(m & low_mask(half));
-        if (r >= c) {
-          r -= c;
-          m >>= half;
-          k += half;
-        }
-      }
-      const int ly = wd / T::WPR, xk = (wd % T::WPR) * 64 + k;
-      const int32_t canon = canon_of(s, nb + ii);
+      const u32 p = s.rt.ipos[ii];
+      const int ly = (int)(p / T::TW), xk = (int)(p % T::TW);
+      const int wd = ly * T::WPR + (xk >> 6);
+      const int32_t canon = canon_of<true>(s, nb + ii);
       if (canon >= d.cap) continue;
       if (d.feat) d.feat[canon] = acc_abs(iacc[o], ly, x0, y0);
       if (d.color) d.color[canon] = (u8)((s.bits[wd] >> (xk & 63)) & 1ull);
-      if (d.parent) d.parent[canon] = canon_of(s, s.rt.ordr[run_rank(s, ly, xk - 1)]);  // interior: x > 0
+      if (d.parent) d.parent[canon] = canon_of<true>(s, s.rt.ordr[run_rank(s, ly, xk - 1)]);  // interior: x > 0
     }
     if (k0 + T::CAPI < nint) __syncthreads();  // the accumulators are cleared next
   }
 
-  // 5. the left neighbour's ids where step 6 reads them
+  // 5. the interior table from positions to row << 8 | rank among the row's
+  // leaders (cheaper to map for the many lookups of steps 6 and 7); the left
+  // neighbour's ids where step 6 reads them
+  __syncthreads();
+  for (int ii = tid; ii < nint; ii += T::NT) {
+    const u32 v = s.rt.ipos[ii];
+    const int ly = (int)(v / T::TW), x = (int)(v % T::TW), j = x >> 6;
+    int rank = popc64(s.lmask[ly * T::WPR + j] & low_mask(x & 63));
+#pragma unroll
+    for (int jj = 0; jj < T::WPR - 1; jj++)
+      if (jj < j) rank += popc64(s.lmask[ly * T::WPR + jj]);
+    s.rt.ipos[ii] = (u16)((ly << 8) | rank);
+  }
   if (tid < th) s.lcanon[tid] = lcv;
   __syncthreads();
 
@@ -2086,7 +2086,7 @@ __global__ void __launch_bounds__(T::NT) k_tile_emit(Src src, Work wk) {
         int x = j * 64 + k;
         int32_t pc;
         if (x == 0) pc = s.lcanon[ly];  // 0 (exterior) at the image's left edge
-        else pc = canon_of(s, s.rt.ordr[run_rank(s, ly, x - 1)]);
+        else pc = canon_of<false>(s, s.rt.ordr[run_rank(s, ly, x - 1)]);
         d.parent[canon] = pc;
       }
     }
@@ -2105,10 +2105,10 @@ __global__ void __launch_bounds__(T::NT) k_tile_emit(Src src, Work wk) {
       const int r2 = r1 + (int)((sw >> 2) & 1u);
       const int r3 = r2 + (int)((sw >> 3) & 1u);
       int32_t lab[4];
-      lab[0] = canon_of(s, s.rt.ordr[r0]);
-      lab[1] = r1 == r0 ? lab[0] : canon_of(s, s.rt.ordr[r1]);
-      lab[2] = r2 == r1 ? lab[1] : canon_of(s, s.rt.ordr[r2]);
-      lab[3] = r3 == r2 ? lab[2] : canon_of(s, s.rt.ordr[r3]);
+      lab[0] = canon_of<false>(s, s.rt.ordr[r0]);
+      lab[1] = r1 == r0 ? lab[0] : canon_of<false>(s, s.rt.ordr[r1]);
+      lab[2] = r2 == r1 ? lab[1] : canon_of<false>(s, s.rt.ordr[r2]);
+      lab[3] = r3 == r2 ? lab[2] : canon_of<false>(s, s.rt.ordr[r3]);
       int32_t* dst = d.labels + (int64_t)(y0 + ly) * d.w + x0 + x;
       if (vec && x + 4 <= tw) {
         store_labels4(dst, lab[0], lab[1], lab[2], lab[3]);
