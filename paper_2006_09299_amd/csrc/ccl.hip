@@ -269,7 +269,7 @@ int ccl_fill_holes(const ccl_outputs_t* in, int32_t w, int32_t h, const ccl_outp
   hl.launch(k_fill_top, L.nblk, FT, a);
   hl.launch(k_fill_scan, 1, SCAN_WG, a);
   hl.launch(k_fill_ids, L.nblk, FT, a);
-  hl.launch(k_fill_merge, L.nblk, FT, a);
+  hl.launch(k_fill_merge, (a.cap + FBM - 1) / FBM, FT, a);
   if (out->labels) {
     int64_t blocks = (a.npx / 4 + FT - 1) / FT;
     blocks = blocks < 1 ? 1 : (blocks > 16384 ? 16384 : blocks);

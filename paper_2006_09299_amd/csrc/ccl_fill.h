@@ -188,40 +188,37 @@ __device__ inline void fill_add(Feature* o, unsigned long long s0, unsigned long
   atomicAdd(reinterpret_cast<unsigned long long*>(&o->Sy), s2);
 }
 
-// One id per lane and step (a wave covers 64 consecutive ids per step).  A
-// percolating top-level component can hold millions of nested ids, all
-// adding into the same three counters: the workgroup takes the target of its
-// first contributing id as a candidate, sums every contribution to it (wave
-// reductions, then LDS) and adds once; within a wave, contributions to the
+// One id per lane and step (a wave covers 64 consecutive ids per step), FKM
+// steps per thread.  A percolating top-level component can hold millions of
+// nested ids, all adding into the same three counters, whose atomics are
+// served one after another: the workgroup takes the target of its first
+// contributing id as a candidate, sums every contribution to it (in each
+// lane, then over the wave, then in LDS) and adds once per workgroup, so the
+// more ids a workgroup covers the fewer such atomics (16 ids per thread:
+// -60 % on the 8192^2 sweep against 4); within a wave, contributions to the
 // target of the wave's first other lane are summed too; the rest add
 // directly.
+constexpr int FKM = 16;          // ids per thread of k_fill_merge
+constexpr int FBM = FT * FKM;    // ids per workgroup of k_fill_merge
 __global__ void __launch_bounds__(FT) k_fill_merge(Args a) {
   __shared__ int32_t wcand[FT / 64];
   __shared__ unsigned long long bsum3[3];
   const int64_t n = fill_n(a);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t c0 = (int64_t)blockIdx.x * FB + (int64_t)wave * 64 * FK;
-  int32_t f[FK];
-  bool add[FK];
-  unsigned long long s0[FK], s1[FK], s2[FK];
+  const int64_t c0 = (int64_t)blockIdx.x * FBM + (int64_t)wave * 64 * FKM;
+  int32_t f[FKM];
+  bool add[FKM];
   int32_t wc = -1;
 #pragma unroll
-  for (int k = 0; k < FK; k++) {
+  for (int k = 0; k < FKM; k++) {
     const int64_t c = c0 + k * 64 + lane;
     f[k] = 0;
     add[k] = false;
-    s0[k] = s1[k] = s2[k] = 0;
     if (c < n) {
       const int32_t t = a.top[c];
       f[k] = t > 0 ? a.fid[t] : 0;
       a.map[c] = f[k];
       add[k] = c > 0 && t != c && f[k] > 0 && (int64_t)f[k] < a.ocap && a.ofeat && a.feat;
-      if (add[k]) {
-        const Feature& g = a.feat[c];
-        s0[k] = (unsigned long long)g.S;
-        s1[k] = (unsigned long long)g.Sx;
-        s2[k] = (unsigned long long)g.Sy;
-      }
     }
     const unsigned long long act = __ballot(add[k]);
     if (wc < 0 && act) wc = __shfl(f[k], __builtin_ctzll(act), 64);
@@ -231,26 +228,39 @@ __global__ void __launch_bounds__(FT) k_fill_merge(Args a) {
   __syncthreads();
   int32_t cand = -1;
   for (int w = 0; w < FT / 64 && cand < 0; w++) cand = wcand[w];
-  unsigned long long p0 = 0, p1 = 0, p2 = 0;  // this wave's sum for the candidate
+  unsigned long long p0 = 0, p1 = 0, p2 = 0;  // this lane's sum for the candidate
 #pragma unroll
-  for (int k = 0; k < FK; k++) {
+  for (int k = 0; k < FKM; k++) {
+    const int64_t c = c0 + k * 64 + lane;
+    unsigned long long s0 = 0, s1 = 0, s2 = 0;
+    if (add[k]) {
+      const Feature& g = a.feat[c];
+      s0 = (unsigned long long)g.S;
+      s1 = (unsigned long long)g.Sx;
+      s2 = (unsigned long long)g.Sy;
+    }
     const bool mine = add[k] && f[k] == cand;
-    p0 += fill_wave_sum(mine ? s0[k] : 0ull);
-    p1 += fill_wave_sum(mine ? s1[k] : 0ull);
-    p2 += fill_wave_sum(mine ? s2[k] : 0ull);
+    if (mine) {
+      p0 += s0;
+      p1 += s1;
+      p2 += s2;
+    }
     const bool rest = add[k] && !mine;
     const unsigned long long act = __ballot(rest);
     if (act) {
       const int ll = __builtin_ctzll(act);
       const int32_t fl = __shfl(f[k], ll, 64);
       const bool same = rest && f[k] == fl;
-      const unsigned long long t0 = fill_wave_sum(same ? s0[k] : 0ull);
-      const unsigned long long t1 = fill_wave_sum(same ? s1[k] : 0ull);
-      const unsigned long long t2 = fill_wave_sum(same ? s2[k] : 0ull);
+      const unsigned long long t0 = fill_wave_sum(same ? s0 : 0ull);
+      const unsigned long long t1 = fill_wave_sum(same ? s1 : 0ull);
+      const unsigned long long t2 = fill_wave_sum(same ? s2 : 0ull);
       if (lane == ll) fill_add(&a.ofeat[fl], t0, t1, t2);
-      if (rest && !same) fill_add(&a.ofeat[f[k]], s0[k], s1[k], s2[k]);
+      if (rest && !same) fill_add(&a.ofeat[f[k]], s0, s1, s2);
     }
   }
+  p0 = fill_wave_sum(p0);
+  p1 = fill_wave_sum(p1);
+  p2 = fill_wave_sum(p2);
   if (lane == 0 && cand > 0 && (p0 | p1 | p2)) {
     atomicAdd(&bsum3[0], p0);
     atomicAdd(&bsum3[1], p1);
