@@ -161,8 +161,10 @@ int32_t ccl_num_variants(void);
 
 /* [host] Tile rows, tile columns, reduction (1 = LDS hash, 0 = direct
  * atomics), threads per tile workgroup, super-tile side (tiles) and tiles per
- * root-reduction workgroup (1 for direct atomics) of `variant` (any output
- * pointer may be NULL); CCL_EINVAL for an unknown index. */
+ * root-reduction workgroup (1 for direct atomics; the largest group: the
+ * default variants of tiles over 4096 pixels take 128 only for a single image
+ * of at least 256 such groups, else 64) of `variant` (any output pointer may
+ * be NULL); CCL_EINVAL for an unknown index. */
 int ccl_variant_info(int32_t variant, int32_t *tile_h, int32_t *tile_w, int32_t *hash_reduce, int32_t *threads,
                      int32_t *super_tile, int32_t *reduce_group);
 

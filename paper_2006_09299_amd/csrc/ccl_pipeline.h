@@ -141,6 +141,7 @@ struct Work {
                      // (border roots first, then interior roots, raster order)
   int32_t* rcol;     // [tiles*TH] canonical id of the component at each row's last pixel
   uint32_t k1_stride;  // K1's tile order: block b labels tile (b * k1_stride) mod tiles
+  int32_t rh_group;    // tiles per k_reduce_roots workgroup (a power of two)
 };
 
 // Tile of this workgroup: block b takes tile (b * stride) mod tiles, a
@@ -161,8 +162,8 @@ constexpr int SCAN_B = SCAN_T * 4;      // entries per scan block
 
 // Merge schedule: SUP_ tiles per side of a super-tile (its inner seams are
 // merged in LDS by k_seam_local, the rest by k_border_merge); RHT_ tiles per
-// workgroup of the root reduction (0: 64 for tiles of more than 4096 pixels,
-// else 32).
+// workgroup of the root reduction (0: chosen per launch, at most 128 for
+// tiles of more than 4096 pixels, else 32).
 template <int TH_, int TW_, int NT_ = 256, bool FG8_ = true, int SUP_ = 4, int RHT_ = 0>
 struct Tile {
   static constexpr int TH = TH_;
@@ -179,9 +180,10 @@ struct Tile {
   static constexpr bool FG8 = FG8_;
   static constexpr int CAPI = N >= 8192 ? 512 : 256;  // interior accumulators per pass
   static constexpr int SUP = SUP_;
-  static constexpr int RHT = RHT_ ? RHT_ : (N > 4096 ? 64 : 32);
+  static constexpr int RHT = RHT_ ? RHT_ : (N > 4096 ? 128 : 32);
+  static constexpr bool RHT_AUTO = RHT_ == 0;
   static_assert(SUP >= 2 && SUP <= 8, "super-tile side");
-  static_assert(RHT >= 1 && RHT <= 64, "root-reduction group (one wave scans it)");
+  static_assert(RHT >= 1 && RHT <= 256, "root-reduction group");
   static_assert(TW % 64 == 0 && TW <= 256, "tile width (a row rank fits 8 bits)");
   static_assert(TH >= 1 && TH <= 64, "tile height (a column of the tile fits one wave)");
   static_assert(NT >= 128 && NT % 64 == 0, "at least two waves per tile");
@@ -1382,9 +1384,19 @@ constexpr int RH_CAP = 1024;     // LDS hash slots (power of two)
 constexpr int RH_BITS = 10;      // log2(RH_CAP)
 static_assert(1 << RH_BITS == RH_CAP, "hash width");
 // tiles per workgroup: larger groups send fewer atomics to the roots of
-// components that span many tiles (the exterior above all)
+// components that span many tiles (the exterior above all), but a grid of
+// fewer workgroups than compute units leaves the chip idle.  Tiles of more
+// than 4096 pixels of a single image take 128 per group where that still
+// gives 256 groups, else 64 (measured: 16384^2 structured images 45 -> 32 us
+// with 128; 8192^2 images 34 us with 64, 43 with 128, and more with 32; a
+// batch of small images, whose exteriors are many roots, +0.5 % with 128).
 template <class T>
-constexpr int rh_tiles() { return T::RHT; }
+inline int rh_group(int64_t tiles, bool one_image) {
+  int g = T::RHT;
+  if (T::RHT_AUTO)
+    while (g > 64 && (!one_image || (tiles + g - 1) / g < 256)) g >>= 1;
+  return g;
+}
 constexpr int RH_T = 512;        // threads: finds of many nodes in flight at once
 constexpr int RH_EMPTY = -1;
 
@@ -1406,43 +1418,51 @@ __device__ inline void rootacc_clear(RootAcc& a) {
 
 template <class T, class Src>
 __global__ void __launch_bounds__(RH_T) k_reduce_roots(Src src, Work wk, int64_t tiles) {
-  constexpr int RHT = rh_tiles<T>();
-  static_assert(RHT <= 64, "one wave scans the group");
+  constexpr int RHT = T::RHT;  // the largest group
+  static_assert(RHT <= 256 && (RHT & (RHT - 1)) == 0, "one wave scans the group, 64 tiles at a time");
   __shared__ RootAcc tab[RH_CAP];
   __shared__ int pre[RHT + 1];
   __shared__ int64_t tbase[RHT];
   __shared__ int32_t text[RHT];  // exterior node of the tile's image
   __shared__ int used;
   const int tid = threadIdx.x;
-  const int64_t t0 = (int64_t)blockIdx.x * RHT;
-  const int ntl = tiles - t0 < RHT ? (int)(tiles - t0) : RHT;
+  const int G = wk.rh_group;  // this launch's group: a power of two <= RHT
+  const int64_t t0 = (int64_t)blockIdx.x * G;
+  const int ntl = tiles - t0 < G ? (int)(tiles - t0) : G;
   for (int i = tid; i < RH_CAP; i += RH_T) rootacc_clear(tab[i]);
   if (tid < 64) {  // node counts of the group's tiles -> exclusive prefix
-    int c = 0;
-    if (tid < ntl) {
-      const int64_t gt = t0 + tid;
-      const ImgDesc& d = src.by_tile(gt);
-      c = src.ok(d) ? wk.nbt[gt] : 0;
-      tbase[tid] = tile_node_base<T>(d, gt - d.tile0);
-      text[tid] = (int32_t)d.node0;
+    int carry = 0;
+    for (int b = 0; b < G; b += 64) {
+      const int k = b + tid;
+      int c = 0;
+      if (k < ntl) {
+        const int64_t gt = t0 + k;
+        const ImgDesc& d = src.by_tile(gt);
+        c = src.ok(d) ? wk.nbt[gt] : 0;
+        tbase[k] = tile_node_base<T>(d, gt - d.tile0);
+        text[k] = (int32_t)d.node0;
+      }
+      int inc = c;
+      for (int dl = 1; dl < 64; dl <<= 1) {
+        int t = __shfl_up(inc, dl, 64);
+        if (tid >= dl) inc += t;
+      }
+      if (k < G) pre[k] = carry + inc - c;
+      if (k == G - 1) pre[G] = carry + inc;
+      carry += __shfl(inc, 63, 64);
     }
-    int inc = c;
-    for (int dl = 1; dl < 64; dl <<= 1) {
-      int t = __shfl_up(inc, dl, 64);
-      if (tid >= dl) inc += t;
-    }
-    if (tid < RHT) pre[tid] = inc - c;
-    if (tid == RHT - 1) pre[RHT] = inc;
   }
   if (tid == 0) used = 0;
   __syncthreads();
-  const int total = pre[RHT];
+  const int total = pre[G];
   // the group's nodes as one list, RH_T at a time
   for (int base = 0; base < total; base += RH_T) {
     const int i = base + tid;
     if (i < total) {
+      // the tile holding the group's i-th node: the last with pre <= i
       int k = 0;
-      for (int m = 1; m < RHT; m++) k += pre[m] <= i ? 1 : 0;
+      for (int half = G / 2; half >= 1; half >>= 1)
+        if (k + half < G && pre[k + half] <= i) k += half;
       const int node = (int)(tbase[k] + (i - pre[k]));
       const Feature f = wk.gacc[node];
       const int32_t key = wk.gkey[node];
@@ -2189,6 +2209,7 @@ inline Work make_work(const Layout& L, void* ws) {
   w.tord = reinterpret_cast<u16*>(b + L.off_tord);
   w.rcol = reinterpret_cast<int32_t*>(b + L.off_rcol);
   w.k1_stride = 1u;
+  w.rh_group = 1;
   return w;
 }
 
@@ -2252,7 +2273,10 @@ inline void enqueue(Launcher& L, const Src& src, const Work& wk0, int64_t tiles,
   L.launch(k_tile_export<T, Src>, tiles, T::NT, src, wk);
   L.launch(k_seam_local<T, Src>, supers, SL_T, src, wk);
   if (items > 0) L.launch(k_border_merge<T, Src>, (items + 255) / 256, 256, src, wk, items);
-  if (HASH) L.launch(k_reduce_roots<T, Src>, (tiles + rh_tiles<T>() - 1) / rh_tiles<T>(), RH_T, src, wk, tiles);
+  if (HASH) {
+    wk.rh_group = rh_group<T>(tiles, std::is_same<Src, OneImage>::value);
+    L.launch(k_reduce_roots<T, Src>, (tiles + wk.rh_group - 1) / wk.rh_group, RH_T, src, wk, tiles);
+  }
   else L.launch(k_reduce_direct<T, Src>, tiles, 64, src, wk);
   L.launch(k_leaders<T, Src>, tiles, 64, src, wk);
   L.launch(k_scan_reduce<Src>, blocks, SCAN_T, src, wk);

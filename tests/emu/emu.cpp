@@ -356,6 +356,9 @@ int main(int argc, char** argv) {
     case 10: run_images<ccl::Tile<4, 64, 256, true, 2>>(ims, batch); break;
     case 11: run_images<ccl::Tile<4, 64, 256, true, 8, 4>>(ims, batch); break;
     case 12: run_images<ccl::Tile<3, 64, 256, true, 8, 1>>(ims, batch); break;
+    // root-reduction groups of more than one wave of tiles
+    case 13: run_images<ccl::Tile<4, 64, 256, true, 4, 128>>(ims, batch); break;
+    case 14: run_images<ccl::Tile<3, 64, 256, true, 4, 256>>(ims, batch); break;
     default: fprintf(stderr, "bad tile config\n"); return 2;
   }
   FILE* fo = fopen(argv[4], "wb");

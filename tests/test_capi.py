@@ -102,7 +102,7 @@ def test_variants_are_described():
     for v in range(n):
         th, tw, hs, nt, sup, rg = _capi.variant_info(v)
         assert th >= 1 and tw % 64 == 0 and nt % 64 == 0
-        assert 2 <= sup <= 8 and 1 <= rg <= 64 and (hs or rg == 1)
+        assert 2 <= sup <= 8 and 1 <= rg <= 128 and (hs or rg == 1)
         seen.add((th, tw, hs, nt, sup, rg))
         assert _capi.workspace_bytes(1000, 700, v) > 0
     assert len(seen) == n

@@ -123,3 +123,17 @@ def test_emulated_merge_schedules(cfg):
     imgs = _cases(600 + cfg, 3, 36, 300)
     for img, r in zip(imgs, emu_runner.run(imgs, tile_cfg=cfg, batch=True, pitch_pad=7)):
         _assert_same(img, r)
+
+
+@pytest.mark.parametrize("cfg", [13, 14])
+def test_emulated_large_reduction_groups(cfg):
+    """Root-reduction groups of 128 and 256 tiles, whose node-count prefix is
+    taken 64 tiles at a time: images of more than 64, 128 and 256 tiles, so
+    that a group's second and later chunks, and a ragged last group, occur."""
+    imgs = [synth.bernoulli_blocks(48, 520, 0.5, 1, 3),  # 12 x 9 tiles of 4 x 64
+            synth.bernoulli_blocks(60, 1000, 0.4, 2, 4)]  # 15 x 16 or 20 x 16 tiles
+    for img, r in zip(imgs, emu_runner.run(imgs, tile_cfg=cfg)):
+        _assert_same(img, r)
+    imgs = _cases(700 + cfg, 2, 40, 600)
+    for img, r in zip(imgs, emu_runner.run(imgs, tile_cfg=cfg, batch=True, pitch_pad=3)):
+        _assert_same(img, r)
