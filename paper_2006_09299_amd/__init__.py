@@ -58,7 +58,10 @@ class Buffers:
 
     def __init__(self, w: int, h: int, cap: int, device, labels: bool = True, variant: Optional[int] = None):
         self.w, self.h, self.cap = int(w), int(h), int(cap)
-        # None: the variant ccl_label itself runs for this size
+        # None: the environment's override (CCL_VARIANT / CCL_TILE), else the
+        # variant ccl_label itself runs for this size
+        if variant is None:
+            variant = _capi.env_variant()
         self.variant = _capi.variant_for(w, h) if variant is None else int(variant)
         self.labels = torch.empty((h, w), dtype=torch.int32, device=device) if labels else None
         self.features = torch.empty((cap, 5), dtype=torch.int64, device=device)

@@ -3,6 +3,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+from typing import Optional
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libccl.so")
@@ -178,6 +179,34 @@ def variant_for(w: int, h: int) -> int:
     v = int(lib().ccl_variant_for(int(w), int(h)))
     check(v if v < 0 else 0, "ccl_variant_for")
     return v
+
+
+VARIANT_ENV, TILE_ENV = "CCL_VARIANT", "CCL_TILE"
+
+
+def env_variant() -> Optional[int]:
+    """Variant forced from the environment, for experiments: CCL_VARIANT=<index>
+    or CCL_TILE=<rows>x<cols> (the lowest-numbered variant of that tile shape);
+    None when neither is set.  Calls that are given a variant ignore it."""
+    n = num_variants()
+    s = os.environ.get(VARIANT_ENV, "").strip()
+    if s:
+        try:
+            v = int(s)
+        except ValueError:
+            v = -1
+        if not 0 <= v < n:
+            raise ValueError(f"{VARIANT_ENV}={s!r}: expected a variant index in [0, {n})")
+        return v
+    s = os.environ.get(TILE_ENV, "").strip().lower()
+    if s:
+        for v in range(n):
+            th, tw = variant_info(v)[:2]
+            if s == f"{th}x{tw}":
+                return v
+        shapes = sorted({"%dx%d" % tuple(variant_info(v)[:2]) for v in range(n)})
+        raise ValueError(f"{TILE_ENV}={s!r}: no compiled variant has that tile shape ({', '.join(shapes)})")
+    return None
 
 
 def num_variants() -> int:

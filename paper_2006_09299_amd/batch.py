@@ -119,9 +119,13 @@ class BatchPlan:
         return out
 
 
-def label_batch(imgs: Sequence[torch.Tensor], variant: int = 0) -> List[Result]:
+def label_batch(imgs: Sequence[torch.Tensor], variant: Optional[int] = None) -> List[Result]:
     """Label a list of device images in one batched launch sequence; grows
-    the tables and reruns the batch if an image had more components."""
+    the tables and reruns the batch if an image had more components.
+    variant None: the environment's override (CCL_VARIANT / CCL_TILE), else 0."""
+    if variant is None:
+        variant = _capi.env_variant()
+        variant = 0 if variant is None else variant
     caps = None
     while True:
         plan = BatchPlan(imgs, variant=variant, caps=caps)

@@ -84,7 +84,11 @@ def time_variant(imgs: Sequence[torch.Tensor], variant: int, reps: int = 3) -> f
 
 def autotune(imgs: Sequence[torch.Tensor], variants: Optional[Sequence[int]] = None, reps: int = 3,
              force: bool = False, path: Optional[str] = None) -> int:
-    """Best variant for batches like `imgs` (cached)."""
+    """Best variant for batches like `imgs` (cached); a variant forced from
+    the environment (CCL_VARIANT / CCL_TILE) is returned untimed."""
+    forced = _capi.env_variant()
+    if forced is not None:
+        return forced
     path = path or cache_path()
     key = workload_key(imgs)
     data = _load(path)

@@ -161,3 +161,26 @@ def test_noalloc_refuses_oversize_and_bad_arguments_on_host():
     assert L.ccl_label_noalloc(None, 8, 8, 8, ctypes.byref(out), None) == _capi.CCL_EINVAL
     assert L.ccl_label_noalloc(fake, 64, 64, 63, ctypes.byref(out), None) == _capi.CCL_EINVAL
     assert L.ccl_label_noalloc(fake, 64, 64, 64, None, None) == _capi.CCL_EINVAL
+
+
+def test_environment_variant_override(monkeypatch):
+    """CCL_VARIANT / CCL_TILE force a variant for experiments (host logic)."""
+    monkeypatch.delenv(_capi.VARIANT_ENV, raising=False)
+    monkeypatch.delenv(_capi.TILE_ENV, raising=False)
+    assert _capi.env_variant() is None
+    n = _capi.num_variants()
+    monkeypatch.setenv(_capi.VARIANT_ENV, str(n - 1))
+    assert _capi.env_variant() == n - 1
+    for bad in (str(n), "-1", "x"):
+        monkeypatch.setenv(_capi.VARIANT_ENV, bad)
+        with pytest.raises(ValueError):
+            _capi.env_variant()
+    monkeypatch.delenv(_capi.VARIANT_ENV)
+    for v in range(n):
+        th, tw = _capi.variant_info(v)[:2]
+        monkeypatch.setenv(_capi.TILE_ENV, f"{th}x{tw}")
+        f = _capi.env_variant()
+        assert f <= v and _capi.variant_info(f)[:2] == (th, tw)
+    monkeypatch.setenv(_capi.TILE_ENV, "7x7")
+    with pytest.raises(ValueError):
+        _capi.env_variant()
