@@ -157,7 +157,8 @@ constexpr u32 HI = 0x80000000u;
 // exterior's partial sums over them by workgroup (one address taking the
 // atomics of every workgroup serialises them), and k_border_canon adds them up.
 constexpr int EXT_REP = 32;
-constexpr int SCAN_T = 256;             // threads of the scan kernels
+constexpr int SCAN_T = 256;             // threads of the scan kernels (whole waves)
+static_assert(SCAN_T % 64 == 0, "the block scan works in whole waves");
 constexpr int SCAN_B = SCAN_T * 4;      // entries per scan block
 
 // Merge schedule: SUP_ tiles per side of a super-tile (its inner seams are
@@ -1571,6 +1572,8 @@ __global__ void __launch_bounds__(64) k_leaders(Src src, Work wk) {
   __shared__ u16 pre[T::BCAP + 1];
   __shared__ u32 first[T::TH];
   __shared__ u32 cnt[T::TH];
+  __shared__ int32_t rl[T::BCAP];  // the node's root, HI set when the node leads its component
+  __shared__ int32_t gr[T::BCAP];  // the node's row and rank from K1
   const int64_t gt = blockIdx.x;
   const ImgDesc& d = src.by_tile(gt);
   if (!src.ok(d)) return;
@@ -1594,7 +1597,10 @@ __global__ void __launch_bounds__(64) k_leaders(Src src, Work wk) {
       int node = (int)(nbase + i);
       int r = wk.gpar[node];
       lead = r != (int)d.node0 && wk.gminkey[r] == wk.gkey[node];
-      int ly = (wk.grank[node] >> 16) & 63;
+      const int g = wk.grank[node];
+      int ly = (g >> 16) & 63;
+      rl[i] = lead ? (int)((u32)r | HI) : r;
+      gr[i] = g;
       atomicMin(&first[ly], (u32)i);
       if (lead) atomicAdd(&cnt[ly], 1u);
     }
@@ -1604,12 +1610,13 @@ __global__ void __launch_bounds__(64) k_leaders(Src src, Work wk) {
   }
   if (lane == 0) pre[nb] = (u16)carry;
   __syncthreads();
-  for (int i = lane; i < nb; i += 64) {
+  for (int i = lane; i < nb; i += 64) {  // from LDS: no second round of dependent loads
     int node = (int)(nbase + i);
-    int g = wk.grank[node];
+    int g = gr[i];
     int ly = (g >> 16) & 63;
-    int r = wk.gpar[node];
-    bool lead = r != (int)d.node0 && wk.gminkey[r] == wk.gkey[node];
+    const int rv = rl[i];
+    const bool lead = rv < 0;
+    const int r = rv & 0x7FFFFFFF;
     int rank = (g & 0xFFFF) + (int)pre[i] - (int)pre[first[ly]];
     wk.grank[node] = rank | (ly << 16) | (lead ? (int)HI : 0);
     if (lead) wk.rcanon[r] = rank;  // the component's rank in its first pixel's cell
@@ -1622,26 +1629,31 @@ __global__ void __launch_bounds__(64) k_leaders(Src src, Work wk) {
 // ---------------------------------------------------------------------------
 // scan of the count grid, per image: base = 1 + exclusive prefix
 
-__device__ inline u32 block_excl_scan(u32 v, u32* tmp, u32& total) {
-  // Hillis-Steele over SCAN_T threads in LDS
-  const int t = threadIdx.x;
-  tmp[t] = v;
-  __syncthreads();
-  for (int dlt = 1; dlt < SCAN_T; dlt <<= 1) {
-    u32 a = t >= dlt ? tmp[t - dlt] : 0u;
-    __syncthreads();
-    tmp[t] += a;
-    __syncthreads();
+__device__ inline u32 block_excl_scan(u32 v, u32* wsum, u32& total) {
+  // each wave scans its 64 values in registers; the waves' totals go
+  // through LDS (two barriers; wsum holds SCAN_T / 64 entries)
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  u32 inc = v;
+  for (int dl = 1; dl < 64; dl <<= 1) {
+    u32 x = __shfl_up(inc, dl, 64);
+    if (lane >= dl) inc += x;
   }
-  total = tmp[SCAN_T - 1];
-  u32 r = tmp[t] - v;
+  if (lane == 63) wsum[wv] = inc;
   __syncthreads();
-  return r;
+  u32 before = 0, all = 0;
+  for (int k = 0; k < SCAN_T / 64; k++) {
+    const u32 s = wsum[k];
+    before += k < wv ? s : 0u;
+    all += s;
+  }
+  total = all;
+  __syncthreads();  // wsum is free for the next call
+  return before + inc - v;
 }
 
 template <class Src>
 __global__ void __launch_bounds__(SCAN_T) k_scan_reduce(Src src, Work wk) {
-  __shared__ u32 tmp[SCAN_T];
+  __shared__ u32 tmp[SCAN_T / 64];
   const int64_t gb = blockIdx.x;
   const ImgDesc& d = src.by_block(gb);
   if (!src.ok(d)) return;
@@ -1659,7 +1671,7 @@ __global__ void __launch_bounds__(SCAN_T) k_scan_reduce(Src src, Work wk) {
 
 template <class Src>
 __global__ void __launch_bounds__(SCAN_T) k_scan_apply(Src src, Work wk) {
-  __shared__ u32 tmp[SCAN_T];
+  __shared__ u32 tmp[SCAN_T / 64];
   const int64_t gb = blockIdx.x;
   const ImgDesc& d = src.by_block(gb);
   if (!src.ok(d)) return;
