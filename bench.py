@@ -158,6 +158,15 @@ def host_cpu():
     return {"model": model, "usable_cores": usable, "logical_cpus": os.cpu_count()}
 
 
+def _variant_config(shape):
+    """The compiled variant a single-image call takes for this shape."""
+    from paper_2006_09299_amd import _capi
+    h, w = shape
+    v = _capi.variant_for(w, h)
+    th, tw, _, threads, sup, _ = _capi.variant_info(v)
+    return {"variant": v, "tile": [th, tw], "threads": threads, "super_tile": sup}
+
+
 def run_gpu(work, steps: int, warmup: int):
     import torch
     import paper_2006_09299_amd as ccl
@@ -763,7 +772,7 @@ def main():
         "dtype": "u8",
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[args.workload], "name": args.workload, "images_per_step": len(work),
-                   "shape": list(work[0][1].shape), "tile": list(ccl.tile_shape())},
+                   "shape": list(work[0][1].shape), **_variant_config(work[0][1].shape)},
         "roofline": head["roofline"],
         "path_hbm": head["path_hbm"],
         "ms_per_image": head["ms_per_image"],

@@ -86,8 +86,9 @@ size_t ccl_workspace_bytes(int32_t w, int32_t h);
 /* [host] The variant (see below) ccl_label, ccl_label_traced and
  * ccl_label_noalloc run for a w x h image: 16 x 128 tiles up to 1.5
  * Mpixel, 32 x 128 tiles up to 6 Mpixel, else 64 x 128 tiles (smaller
- * images are faster with smaller tiles; results never depend on it).
- * CCL_EINVAL for w or h <= 0. */
+ * images are faster with smaller tiles), with super-tiles of 8 x 8 tiles
+ * (variant 9) where the image holds 256 of them or more, else of 4 x 4
+ * (variant 0).  Results never depend on it.  CCL_EINVAL for w or h <= 0. */
 int32_t ccl_variant_for(int32_t w, int32_t h);
 
 /* Label one image: img[y*pitch + x], y < h, x < w.  Enqueues the whole path

@@ -38,8 +38,11 @@ def test_single_image_variant_by_size():
     """ccl_label takes smaller tiles for smaller images; its workspace size is
     that variant's."""
     L = _capi.lib()
+    # super-tiles of 8 x 8 tiles of 64 x 128 where the image holds 256 of them:
+    # 16384 x 8192 holds 16 x 16, 16384 x 7680 16 x 15
     for (w, h), v in [((512, 512), 2), ((1024, 1024), 2), ((1300, 1300), 5), ((2048, 2048), 5),
-                      ((2600, 2400), 5), ((4096, 4096), 0), ((16384, 16384), 0), ((1, 1), 2)]:
+                      ((2600, 2400), 5), ((4096, 4096), 0), ((8192, 8192), 0), ((12288, 12288), 9),
+                      ((16384, 16384), 9), ((16384, 8192), 9), ((16384, 7680), 0), ((1, 1), 2)]:
         assert _capi.variant_for(w, h) == v, (w, h)
         assert L.ccl_workspace_bytes(w, h) == L.ccl_workspace_bytes_v(w, h, v) > 0
         assert _capi.workspace_bytes(w, h) == L.ccl_workspace_bytes(w, h)
