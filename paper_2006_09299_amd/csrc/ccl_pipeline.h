@@ -1158,11 +1158,14 @@ __device__ inline int lnode_of(const Work& wk, const ImgDesc& d, int tx0, int ty
 }
 
 // threads per super-tile: its items are chains of dependent loads, so more
-// of them in flight at once
-constexpr int SL_T = 512;
+// of them in flight at once; super-tiles of 8 x 8 tiles (48 KB of LDS for
+// 64 x 128 tiles, two workgroups per CU) take 1024
+template <class T>
+constexpr int sl_threads() { return T::SUP >= 8 ? 1024 : 512; }
 
 template <class T, class Src>
-__global__ void __launch_bounds__(SL_T) k_seam_local(Src src, Work wk) {
+__global__ void __launch_bounds__(sl_threads<T>()) k_seam_local(Src src, Work wk) {
+  constexpr int SL_T = sl_threads<T>();
   constexpr int NL = T::SUP * T::SUP * T::BCAP;
   static_assert(NL < 65536 && NL % 2 == 0, "local node index fits 16 bits");
   __shared__ u32 lpw[NL / 2];  // 16-bit entries; 32-bit words for the links
@@ -2283,7 +2286,7 @@ inline void enqueue(Launcher& L, const Src& src, const Work& wk0, int64_t tiles,
   Work wk = wk0;
   if constexpr (std::is_same<Src, OneImage>::value) wk.k1_stride = scatter_stride(tiles);
   L.launch(k_tile_export<T, Src>, tiles, T::NT, src, wk);
-  L.launch(k_seam_local<T, Src>, supers, SL_T, src, wk);
+  L.launch(k_seam_local<T, Src>, supers, sl_threads<T>(), src, wk);
   if (items > 0) L.launch(k_border_merge<T, Src>, (items + 255) / 256, 256, src, wk, items);
   if (HASH) {
     wk.rh_group = rh_group<T>(tiles, std::is_same<Src, OneImage>::value);
