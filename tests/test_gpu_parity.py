@@ -2,9 +2,9 @@
 
 Integer outputs, so the bar is bit-exact: labels, features, parent, colour,
 number of labels and Euler number.  Sizes span many tiles (and 4 x 4-tile
-super-tiles) with ragged tails; full-size workloads (all 25 images of the 8192^2 sweep, the 16384^2
-structured images) are compared in full and also checked by size-independent
-properties."""
+super-tiles, 8 x 8 on the largest images) with ragged tails; full-size
+workloads (all 25 images of the 8192^2 sweep, the 16384^2 structured images)
+are compared in full and also checked by size-independent properties."""
 import sys
 
 import numpy as np
@@ -265,3 +265,17 @@ def test_structured_16384(seed):
     if seed == 0:  # the benchmarked image, also without the label image
         _say("16384 structured features-only")
         _features_only(img, o)
+
+
+@pytest.mark.parametrize("h,w,p,g", [(11000, 12000, 0.5, 1), (12288, 12352, 0.3, 4)])
+def test_large_ragged_super_tiles(h, w, p, g):
+    """Images large enough for super-tiles of 8 x 8 tiles in the single-image
+    call, with ragged tiles and super-tiles at the right and bottom edges,
+    element by element."""
+    from paper_2006_09299_amd import _capi
+    assert _capi.variant_for(w, h) == 9 and _capi.variant_info(9)[4] == 8
+    img = synth.bernoulli_blocks(h, w, p, g, 31)
+    _say("large ragged super-tiles", h, w, p, g)
+    r = _run(img)
+    _properties(img, r)
+    _assert_same(r, oracle.label(img))
