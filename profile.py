@@ -135,7 +135,7 @@ def summary(workload: str, outdir: str, copydir: str, md: str):
 
     lines = [f"# rocprofv3 summary: {workload}", "",
              f"Kernel sources digest `{source_digest()}` (bench.py reports `traffic` only for this digest).", "",
-             "Commands (from the repository root, on the GPU box):", "",
+             "Commands (from the repository root, on an MI355X):", "",
              f"    python profile.py run {workload} {outdir}",
              f"    python profile.py copy {copydir}",
              f"    python profile.py summary {workload} {outdir} {copydir} {md}", "",

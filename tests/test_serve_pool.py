@@ -141,8 +141,8 @@ def test_server_entry_points_reject_bad_arguments_on_host():
 def test_server_scheduling_on_a_mock_runtime(tmp_path):
     """ccl_server.cpp built for the host against a mock HIP runtime (copies
     run at once, events finish after a few queries) and stand-ins of the
-    batch entry points; 300 random configurations (see the driver's header
-    for the checks).  Every path must be taken at least once: shrinking
+    batch entry points; 300 random configurations (see the header of the C++
+    test program for the checks).  Every path must be taken at least once: shrinking
     micro-batches, relaunch with the exact capacity, refusal at submit and
     at relaunch, and micro-batches that a batch entry point refuses (each
     request reported with the error, its memory returned)."""
