@@ -122,7 +122,7 @@ struct Work {
   int32_t* gminkey;  // [nodes] at roots: minimum key of the class
   int32_t* grank;    // [nodes] bits 0-15 rank / interior-before, 16-21 row, 31 leader
   int32_t* rcanon;   // [nodes] at roots: rank of the component among those starting in its first pixel's cell
-  int32_t* ncanon;   // [nodes] canonical id of the node's component
+  int32_t* ncanon;   // [nodes] canonical id of the node's component (before K5: the cell of its first pixel)
   Feature* gacc;     // [nodes] partial features; at roots the class sum
   int32_t* nbt;      // [tiles] border nodes per tile
   // border arrays, the two sides of a tile next to each other (indexed by
@@ -1599,7 +1599,13 @@ __global__ void __launch_bounds__(64) k_leaders(Src src, Work wk) {
     if (i < nb) {
       int node = (int)(nbase + i);
       int r = wk.gpar[node];
-      lead = r != (int)d.node0 && wk.gminkey[r] == wk.gkey[node];
+      const bool ext = r == (int)d.node0;
+      const int32_t mk = ext ? 0 : wk.gminkey[r];
+      lead = !ext && mk == wk.gkey[node];
+      if (!ext) {  // the (row, tile column) cell of the component's first pixel, for k_border_canon
+        const int y = mk / d.w, x = mk - y * d.w;
+        wk.ncanon[node] = y * d.ntx + x / T::TW;
+      }
       const int g = wk.grank[node];
       int ly = (g >> 16) & 63;
       rl[i] = lead ? (int)((u32)r | HI) : r;
@@ -1746,13 +1752,9 @@ __global__ void __launch_bounds__(64) k_border_canon(Src src, Work wk) {
     const int node = (int)(nbase + i);
     const int r = wk.gpar[node];
     const int g = wk.grank[node];
+    const int cell = wk.ncanon[node];  // k_leaders left the cell of the component's first pixel here
     int32_t canon = 0;
-    if (r != (int)d.node0) {
-      const int32_t key = wk.gminkey[r];
-      const int32_t rank = wk.rcanon[r];
-      const int y = key / d.w, x = key - y * d.w;
-      canon = wk.cgrid[d.c0 + (int64_t)y * d.ntx + x / T::TW] + rank;
-    }
+    if (r != (int)d.node0) canon = wk.cgrid[d.c0 + cell] + wk.rcanon[r];
     wk.ncanon[node] = canon;
     cl[i] = canon;
     if ((g & (int)HI) && d.feat && canon < d.cap) d.feat[canon] = wk.gacc[r];
